@@ -1,0 +1,192 @@
+"""Throughput of the fused two-component D3Q19 step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
+
+Headline workload: 128^3 periodic box, two species, D3Q19 BGK with
+tau_A = tau_B = 1.0, third-order equilibrium, Shan-Chen G^AB = G^BA = -1.0,
+one droplet of species A with R = 16 (rho_A = 1.0 / 0.03, mirrored for B,
++-1e-3 seeded noise), FP32 storage and arithmetic.  One step = one fused
+kernel launch updating every cell of both species.  MLUPS = cells * steps /
+seconds / 1e6.  The state lives in HBM before the timed region starts.
+
+Prints ONE JSON line.  ``roofline`` prices the fused kernel against HBM: 304
+algorithmic bytes per cell-step (19 populations x 2 species x 4 B, read once
+and written once) divided by the average launch duration measured with HIP
+events on the stream the kernel runs on.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL = {"fp32": 304, "fp16": 152, "bf16": 152}
+ALGO_BYTES_NOTE = "2 species x 19 populations x element size, read + write, per cell-step"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("march.hip", "lattice.h", "launch.h"):
+        with open(os.path.join(ROOT, "paper_1601_01237_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload, storage):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if the kernel is unchanged."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    key = f"{workload}:{storage}"
+    ent = rec.get(key)
+    if not ent or ent.get("kernel_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def time_steps(sim, steps, warmup):
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = sim.stream
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    sim.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps  # ms per step (= per launch)
+
+
+def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1.0, rows=None, zchunk=None):
+    from paper_1601_01237_amd import inputs
+    from paper_1601_01237_amd.sim import Sim
+    if rho0 is None:
+        rho0 = inputs.sphere_droplet(shape, radius=shape[0] / 8.0, seed=0)
+    sim = Sim(rho0, tau=(tau, tau), G=G, storage=storage, solid=solid, rows=rows, zchunk=zchunk)
+    ms = time_steps(sim, steps, warmup)
+    _, _, diag = sim.moments(want_fields=False)
+    n = int(np.prod(shape))
+    sim.close()
+    mlups = n / (ms * 1e-3) / 1e6
+    gbs = BYTES_PER_CELL[storage] * n / (ms * 1e-3) / 1e9
+    return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, nonfinite=diag["nonfinite"], n=n)
+
+
+def cpu_baseline(shape, seconds_budget=30.0):
+    """The FP64 oracle on one step of the headline workload (single thread)."""
+    from oracle import lbm as olbm
+    from paper_1601_01237_amd import inputs
+    rho0 = inputs.sphere_droplet(shape, radius=16.0, seed=0)
+    p = olbm.Params(tau=(1.0, 1.0), G=((0.0, -1.0), (-1.0, 0.0)))
+    f = olbm.init_state(rho0)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        f = olbm.step(f, p)
+        steps += 1
+        if time.perf_counter() - t0 > seconds_budget * 0.5 or steps >= 3:
+            break
+    dt = time.perf_counter() - t0
+    n = int(np.prod(shape))
+    return dict(value=n * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{steps} step(s) of the {shape[2]}x{shape[1]}x{shape[0]} workload, FP64 NumPy, "
+                       f"{dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--n", type=int, default=128)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the z-slab decomposition is a design note).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1601_01237_amd import _lib, inputs
+    _lib.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    n = args.n
+    shape = (n, n, n)
+    rho0 = inputs.sphere_droplet(shape, radius=16.0, seed=0)
+    print(f"[bench] headline {n}^3 fp32 steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    head = run_case(shape, "fp32", args.steps, args.warmup, rho0=rho0)
+    ncell = head["n"]
+    achieved = BYTES_PER_CELL["fp32"] * ncell / (head["ms_per_step"] * 1e-3) / 1e9
+    workload = f"{n}^3"
+    traffic = stored_traffic(workload, "fp32")
+
+    extra = {}
+    if not args.no_extra:
+        steps_big = max(10, args.steps // 10)
+        big = (512, 512, 512)
+        rho_big, _, _ = inputs.random_droplets(big, count=64, rmin=8.0, rmax=24.0, seed=0)
+        for storage in ("fp32", "fp16", "bf16"):
+            print(f"[bench] 512^3 {storage}", file=sys.stderr, flush=True)
+            r = run_case(big, storage, steps_big, 5, rho0=rho_big, tau=0.6)
+            extra[f"512^3_{storage}"] = {k: round(v, 3) for k, v in r.items() if k != "n"}
+        del rho_big
+        print("[bench] walls 384x192x192", file=sys.stderr, flush=True)
+        rho_w, solid = inputs.inclined_channel((192, 192, 384), angle_deg=30.0, radius=32.0, seed=0)
+        r = run_case((192, 192, 384), "fp32", steps_big, 5, rho0=rho_w, solid=solid, tau=0.7)
+        fluid = int((~solid).sum())
+        r["mlups_fluid_only"] = fluid / (r["ms_per_step"] * 1e-3) / 1e6
+        extra["384x192x192_walls_fp32"] = {k: round(v, 3) for k, v in r.items() if k != "n"}
+
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(shape)
+
+    out = {
+        "metric": "MLUPS (2-species D3Q19) + % HBM roofline; FP16-storage & adjoint vs FP32",
+        "value": round(head["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded droplet, +-1e-3 noise)",
+        "config": {"workload": f"{n}^3 periodic, 2 species D3Q19 BGK, tau=1.0, G_AB=G_BA=-1.0, "
+                               f"droplet R=16, FP32", "cells": ncell, "storage": "fp32",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_cell": BYTES_PER_CELL["fp32"],
+                     "kernel": "march_kernel<F32, no walls, Step, 8 rows>"},
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) two-component D3Q19 lattice
+ * Boltzmann library liblbm.so.
+ *
+ * Method: Otomo et al., "Studies of accurate multi-component lattice Boltzmann
+ * models on benchmark cases required for engineering applications"
+ * (arXiv 1601.01237), Sec. 2 and Sec. 4:
+ *   - Eq. (1)   per-species lattice Boltzmann equation, D3Q19, dt = dx = 1;
+ *   - Eq. (2)   BGK collision with relaxation time tau_a;
+ *   - Eq. (3)   third-order equilibrium, T0 = 1/3;
+ *   - Eqs. (4)-(6) species density, mixture density and mixture velocity;
+ *   - Eq. (7)   Shan-Chen inter-component force with G^{aa} = 0;
+ *   - Eqs. (8)-(9) force velocity u_F = u + g/2;
+ *   - Sec. 4    pointwise (halfway) bounce-back and wall potential rho_s^a.
+ * The forcing term, which the paper takes from a citation, is the exact
+ * difference f^eq(rho^a, u + g^a) - f^eq(rho^a, u) of Eq. (3).
+ *
+ * Conventions shared by every entry point
+ *   Grid:     nx * ny * nz cells, x fastest; cell index c = (z*ny + y)*nx + x.
+ *             Every axis is periodic; walls are solid cells inside the box.
+ *   Species:  a = 0 (A) and a = 1 (B).
+ *   Velocity set: LBM_Q = 19 directions in the order returned by
+ *             lbm_velocity_set(): rest, then opposite pairs (1,2), (3,4), ...
+ *   Populations (FP32 interface of lbm_get/set_populations): 2*19*N
+ *             elements, element (a, i, c) at index (a*19 + i)*N + c.
+ *   State:    the library keeps the post-collision, pre-streaming populations
+ *             X (one buffer per time level, two buffers ping-pong).  At time t
+ *             the current state lives in buf_a if t is even, buf_b if odd.
+ *             Stored states and adjoint arrays use the plane-major layout
+ *             X[z][a][i][y][x]: element (a, i, x, y, z) at index
+ *             ((z*2 + a)*19 + i)*nx*ny + y*nx + x, so that one z plane of all
+ *             38 populations is one contiguous block.
+ *             The pre-collision populations of Eq. (1) at time t are the pull
+ *             f_i(x) = X_i(x - c_i), or X_opp(i)(x) if x - c_i is solid.
+ *   Memory:   every array pointer is DEVICE memory owned by the caller unless
+ *             stated otherwise; the library keeps non-owning pointers, so the
+ *             arrays must outlive the context.  The library itself allocates
+ *             only its context, a per-cell link mask when walls are given
+ *             (4 bytes per cell) and a small reduction buffer.
+ *   Streams:  every call is enqueued asynchronously on the stream given to
+ *             lbm_init (a hipStream_t passed as void*; NULL = null stream).
+ *             Argument checks are synchronous and return LBM_EINVAL /
+ *             LBM_ENOTSUP before anything is enqueued; a failed launch
+ *             returns LBM_EHIP.  No call synchronises the stream.
+ *   Threads:  a context is not thread-safe; use one context per stream.
+ *   Errors:   no exception, abort or exit crosses this interface.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,    /* bad argument (null pointer, size, tau <= 1/2, ...)  */
+  LBM_EHIP = -2,      /* a HIP runtime call or kernel launch failed          */
+  LBM_ESTATE = -3,    /* call not valid in the context's current state       */
+  LBM_EUNSTABLE = -4, /* non-finite values found (reported by callers that   */
+                      /* read the diagnostic vector)                         */
+  LBM_ENOTSUP = -5    /* valid request outside what this build supports      */
+} lbm_status;
+
+/* Storage of the population buffers.  Arithmetic is always FP32.  The
+ * 16-bit forms store X_i - w_i * rho_shift[a] rounded to nearest even. */
+typedef enum { LBM_FP32 = 0, LBM_FP16 = 1, LBM_BF16 = 2 } lbm_storage;
+
+#define LBM_Q 19
+#define LBM_DIAG_LEN 16
+
+/* Indices into the diagnostic vector written by lbm_moments (FP64). */
+enum {
+  LBM_DIAG_MASS_A = 0,   /* sum over fluid cells of rho^A                       */
+  LBM_DIAG_MASS_B = 1,   /* sum over fluid cells of rho^B                       */
+  LBM_DIAG_MOM_X = 2,    /* sum of rho * u_F, x y z (Eqs. 8-9)                  */
+  LBM_DIAG_MOM_Y = 3,
+  LBM_DIAG_MOM_Z = 4,
+  LBM_DIAG_MAX_UF = 5,   /* max |u_F| over fluid cells (spurious velocity)      */
+  LBM_DIAG_NONFINITE = 6,/* fluid cells with a non-finite rho^A, rho^B or u_F   */
+  LBM_DIAG_N_FLUID = 7,  /* number of fluid cells                               */
+  LBM_DIAG_P_IN_SUM = 8, /* sum of p over fluid cells with |x - centre| < r_in  */
+  LBM_DIAG_N_IN = 9,
+  LBM_DIAG_P_OUT_SUM = 10,/* sum of p over fluid cells with |x - centre| > r_out */
+  LBM_DIAG_N_OUT = 11,
+  LBM_DIAG_N_THR = 12,   /* fluid cells with rho^A > thr                        */
+  LBM_DIAG_SDX_THR = 13, /* sum over those cells of the minimum-image offset    */
+  LBM_DIAG_SDY_THR = 14, /* from the centre, x y z                              */
+  LBM_DIAG_SDZ_THR = 15
+};
+
+typedef struct {
+  int32_t nx, ny, nz;  /* >= 1 each; 2*19*N elements of the storage type     */
+                       /* per buffer; N * element size must stay below 4 GiB */
+  int32_t storage;     /* lbm_storage                                        */
+  double tau[2];       /* relaxation times tau_A, tau_B (Eq. 2), > 1/2       */
+  double G[2][2];      /* interaction matrix G^{ab} of Eq. (7), paper sign:  */
+                       /* repulsion is G[0][1], G[1][0] < 0.  G[a][a] must   */
+                       /* be 0 (Sec. 2), else LBM_ENOTSUP.                   */
+  double rho_shift[2]; /* shift of the 16-bit storage forms (ignored in FP32)*/
+  double rho_wall[2];  /* wall potential rho_s^a (Sec. 4): the density a     */
+                       /* solid neighbour contributes to the Eq. (7) sum     */
+} lbm_params;
+
+/* Region parameters of the diagnostic vector (host struct). */
+typedef struct {
+  double center[3];    /* x, y, z; offsets use the periodic minimum image    */
+  double r_in, r_out;  /* Laplace-pressure averaging radii                   */
+  double thr;          /* droplet threshold on rho^A                         */
+} lbm_diag_region;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Library version (major*10000 + minor*100 + patch).  Pure host call. */
+int32_t lbm_version(void);
+
+/* Copies the D3Q19 velocity set in the library's order: c[3*i + k] is
+ * component k (x, y, z) of c_i; w[i] its weight (1/3, 1/18, 1/36 -- the
+ * isotropic weights of Sec. 2).  Either pointer may be NULL.  Host memory.
+ * Pure host call, needs no GPU. */
+lbm_status lbm_velocity_set(int32_t *c, double *w);
+
+/* Human-readable name of a status code (static string). */
+const char *lbm_status_str(lbm_status s);
+
+/* Creates a context and writes the rest state at t = 0 into buf_a.
+ *   p      host; copied.
+ *   buf_a, buf_b  device, 2*19*N elements of the storage type each.
+ *   solid  device, N bytes, nonzero = wall cell; NULL = no walls.
+ *   rho0   device, 2*N doubles: rho0^a(c) at index a*N + c.  The initial
+ *          pre-collision state is f_i^a = w_i rho0^a (Eq. 3 at u = 0) on fluid
+ *          cells; solid cells carry no populations.
+ *   stream hipStream_t as void*.
+ * On success *ctx owns a host struct and (walls only) a device link mask.
+ * Allocation failures return LBM_EHIP and leave *ctx NULL. */
+lbm_status lbm_init(lbm_ctx **ctx, const lbm_params *p, void *buf_a, void *buf_b,
+                    const uint8_t *solid, const double *rho0, void *stream);
+
+/* Advances n >= 0 time steps of Eq. (1) (collide with Eqs. 2-3 and 7, then
+ * stream with bounce-back); t += n.  One fused kernel launch per step. */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Observables of the current time t (Eqs. 4-9).  Any output may be NULL.
+ *   rho    device float, 2*N: rho^a(c) at a*N + c (0 on solid cells).
+ *   u_f    device float, 3*N: component k of u_F at k*N + c (0 on solid).
+ *   diag   device double, LBM_DIAG_LEN entries (see the index list above);
+ *          pressure p = T0 (rho^A + rho^B) - G T0 rho^A rho^B with
+ *          G = (G[0][1] + G[1][0]) / 2.
+ *   region host, may be NULL (centre of the box, r_in = 0, r_out = inf,
+ *          thr = 0.515). */
+lbm_status lbm_moments(lbm_ctx *ctx, float *rho, float *u_f, double *diag,
+                       const lbm_diag_region *region);
+
+/* Pre-collision populations f_i^a(x, t) of the current time as FP32
+ * (device, 2*19*N, index (a*19 + i)*N + c); zero on solid cells. */
+lbm_status lbm_get_populations(lbm_ctx *ctx, float *f);
+
+/* Replaces the current state by the given pre-collision populations
+ * (device FP32, 2*19*N, index (a*19 + i)*N + c).  Values on solid cells are
+ * ignored. */
+lbm_status lbm_set_populations(lbm_ctx *ctx, const float *f);
+
+/* Current time level t. */
+int64_t lbm_time(const lbm_ctx *ctx);
+
+/* Sets t (e.g. after restoring a checkpoint into the matching buffer). */
+lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
+
+/* Tiling of the fused kernels: rows of cells per workgroup (4 or 8) and
+ * z planes marched per workgroup (>= 1; 0 picks a default from the grid).
+ * Results do not depend on this choice (bitwise).  Host-side setting. */
+lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t rows, int32_t zchunk);
+
+/* ---- Adjoint (reverse mode) of one step, FP32 storage only ------------
+ * Let X_t be the stored state at t and L a scalar objective.  With
+ * lam_{t+1} = dL/dX_{t+1} (device float, 2*19*N, in the plane-major layout of
+ * the stored state, see below) this computes
+ * lam_t = dL/dX_t, the transpose of one step at X_t (collision with the
+ * Eq. 7 gather, then pull streaming with bounce-back).  It also ADDS to
+ * dparams (device double[3]): dL/dG (for tied G^{AB} = G^{BA}), dL/dtau_A,
+ * dL/dtau_B.  If drho0 (device double, 2*N) is not NULL it receives
+ * sum_i w_i dL/df_i^a(x, t): at t = 0 this is dL/drho0 of lbm_init.
+ *   x_t    device, 2*19*N of the storage type: X_t (may be a saved copy).
+ *   work   device scratch; work_bytes must be at least
+ *          lbm_adjoint_work_bytes(ctx) for the current tiling (else
+ *          LBM_EINVAL).
+ * lam_in and lam_out must not alias each other or x_t. */
+size_t lbm_adjoint_work_bytes(const lbm_ctx *ctx);
+lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *x_t, const float *lam_in,
+                            float *lam_out, void *work, size_t work_bytes,
+                            double *dparams, double *drho0);
+
+/* dL/dX_T for an objective of the densities at time T: given
+ * grad_rho (device float, 2*N, index a*N + c) = dL/drho^a(x, T), writes lam
+ * (device float, 2*19*N, plane-major) = dL/dX_T.  Solid cells get zero. */
+lbm_status lbm_adjoint_seed(lbm_ctx *ctx, const float *grad_rho, float *lam);
+
+/* Frees the context and what the library allocated; NULL is a no-op.
+ * Waits for the context's stream first. */
+lbm_status lbm_destroy(lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

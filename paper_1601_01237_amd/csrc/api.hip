@@ -1,0 +1,285 @@
+// C ABI of liblbm.so (declared in include/lbm.h): argument checks, context
+// bookkeeping and kernel launches on the caller's stream.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <new>
+
+#include "../../include/lbm.h"
+#include "launch.h"
+
+using namespace lbm;
+
+struct lbm_ctx {
+  lbm_params p;
+  Grid g;
+  Phys ph;
+  Storage storage;
+  void* buf[2];
+  uint32_t* links;     // owned; null without walls
+  hipStream_t stream;
+  int64_t t;
+  int rows, zchunk;
+  double* partials;    // owned reduction scratch
+  size_t partials_cap; // doubles
+};
+
+namespace {
+
+size_t elem_size(Storage s) { return s == Storage::F32 ? 4 : 2; }
+
+lbm_status from_hip(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
+
+Tiling tiling(const lbm_ctx* c) { return make_tiling(c->g, c->rows, c->zchunk); }
+
+lbm_status ensure_partials(lbm_ctx* c, size_t need) {
+  if (need <= c->partials_cap) return LBM_OK;
+  if (c->partials) {
+    // The previous buffer may still be read by work queued on the stream.
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM_EHIP;
+    (void)hipFree(c->partials);
+    c->partials = nullptr;
+    c->partials_cap = 0;
+  }
+  if (hipMalloc(reinterpret_cast<void**>(&c->partials), need * sizeof(double)) != hipSuccess) {
+    c->partials = nullptr;
+    return LBM_EHIP;
+  }
+  c->partials_cap = need;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lbm_version(void) { return 10000; }
+
+lbm_status lbm_velocity_set(int32_t* c, double* w) {
+  for (int i = 0; i < Q; ++i) {
+    if (c) {
+      c[3 * i + 0] = CX[i];
+      c[3 * i + 1] = CY[i];
+      c[3 * i + 2] = CZ[i];
+    }
+    if (w) w[i] = weight_d(i);
+  }
+  return LBM_OK;
+}
+
+const char* lbm_status_str(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_EHIP: return "HIP runtime error";
+    case LBM_ESTATE: return "invalid state";
+    case LBM_EUNSTABLE: return "non-finite values (unstable run)";
+    case LBM_ENOTSUP: return "not supported";
+  }
+  return "unknown status";
+}
+
+lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, const uint8_t* solid,
+                    const double* rho0, void* stream) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  if (!p || !buf_a || !buf_b || !rho0 || buf_a == buf_b) return LBM_EINVAL;
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return LBM_EINVAL;
+  if (p->storage < LBM_FP32 || p->storage > LBM_BF16) return LBM_EINVAL;
+  for (int a = 0; a < 2; ++a) {
+    if (!(p->tau[a] > 0.5) || !std::isfinite(p->tau[a])) return LBM_EINVAL;
+    if (!std::isfinite(p->rho_shift[a]) || !std::isfinite(p->rho_wall[a])) return LBM_EINVAL;
+    for (int b = 0; b < 2; ++b)
+      if (!std::isfinite(p->G[a][b])) return LBM_EINVAL;
+  }
+  if (p->G[0][0] != 0.0 || p->G[1][1] != 0.0) return LBM_ENOTSUP;
+  const uint64_t nxy = static_cast<uint64_t>(p->nx) * p->ny;
+  const uint64_t n = nxy * p->nz;
+  const Storage st = static_cast<Storage>(p->storage);
+  // Within one population array, offsets are 32-bit.
+  if (n * elem_size(st) >= (1ull << 32) || n >= (1ull << 31)) return LBM_ENOTSUP;
+
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_EHIP;
+  c->p = *p;
+  c->g = Grid{p->nx, p->ny, p->nz, static_cast<uint32_t>(nxy), n};
+  for (int a = 0; a < 2; ++a) {
+    c->ph.omega[a] = static_cast<float>(1.0 / p->tau[a]);
+    c->ph.rho_wall[a] = static_cast<float>(p->rho_wall[a]);
+    c->ph.shift[a] = st == Storage::F32 ? 0.0f : static_cast<float>(p->rho_shift[a]);
+  }
+  c->ph.g_ab = static_cast<float>(p->G[0][1]);
+  c->ph.g_ba = static_cast<float>(p->G[1][0]);
+  c->storage = st;
+  c->buf[0] = buf_a;
+  c->buf[1] = buf_b;
+  c->links = nullptr;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->t = 0;
+  c->rows = 8;
+  c->zchunk = 0;
+  c->partials = nullptr;
+  c->partials_cap = 0;
+
+  hipError_t e = hipSuccess;
+  if (solid) {
+    if (hipMalloc(reinterpret_cast<void**>(&c->links), n * sizeof(uint32_t)) != hipSuccess) {
+      delete c;
+      return LBM_EHIP;
+    }
+    e = launch_links(c->g, solid, c->links, c->stream);
+  }
+  // Both buffers get the rest state, so wall cells (never written by a step)
+  // hold the same defined values in either time level.
+  if (e == hipSuccess) e = launch_init(st, c->g, c->ph, c->links, rho0, buf_a, c->stream);
+  if (e == hipSuccess) e = launch_init(st, c->g, c->ph, c->links, rho0, buf_b, c->stream);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(c->stream);
+    if (c->links) (void)hipFree(c->links);
+    delete c;
+    return LBM_EHIP;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n) {
+  if (!c || n < 0) return LBM_EINVAL;
+  const Tiling t = tiling(c);
+  if (t.blocks <= 0) return LBM_ENOTSUP;
+  for (int64_t k = 0; k < n; ++k) {
+    MarchIO io;
+    io.src = c->buf[c->t & 1];
+    io.dst = c->buf[(c->t + 1) & 1];
+    io.links = c->links;
+    const hipError_t e = launch_march(c->storage, Mode::Step, c->g, c->ph, t, io, c->stream);
+    if (e != hipSuccess) return LBM_EHIP;
+    ++c->t;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx* c, float* rho, float* u_f, double* diag, const lbm_diag_region* region) {
+  if (!c) return LBM_EINVAL;
+  const Tiling t = tiling(c);
+  if (t.blocks <= 0) return LBM_ENOTSUP;
+  if (diag) {
+    const lbm_status s = ensure_partials(c, static_cast<size_t>(t.blocks) * 16);
+    if (s != LBM_OK) return s;
+  }
+  MarchIO io;
+  io.src = c->buf[c->t & 1];
+  io.links = c->links;
+  io.rho_out = rho;
+  io.uf_out = u_f;
+  io.partials = diag ? c->partials : nullptr;
+  Region R;
+  if (region) {
+    R.cx = static_cast<float>(region->center[0]);
+    R.cy = static_cast<float>(region->center[1]);
+    R.cz = static_cast<float>(region->center[2]);
+    R.r_in2 = static_cast<float>(region->r_in * region->r_in);
+    R.r_out2 = static_cast<float>(region->r_out * region->r_out);
+    R.thr = static_cast<float>(region->thr);
+  } else {
+    R.cx = 0.5f * c->g.nx;
+    R.cy = 0.5f * c->g.ny;
+    R.cz = 0.5f * c->g.nz;
+    R.r_in2 = 0.0f;
+    R.r_out2 = INFINITY;
+    R.thr = 0.515f;
+  }
+  R.p_g = static_cast<float>(0.5 * (c->p.G[0][1] + c->p.G[1][0]));
+  io.region = R;
+  if (!diag) {
+    // Partials are still written by the kernel: give it the scratch.
+    const lbm_status s = ensure_partials(c, static_cast<size_t>(t.blocks) * 16);
+    if (s != LBM_OK) return s;
+    io.partials = c->partials;
+  }
+  hipError_t e = launch_march(c->storage, Mode::Moments, c->g, c->ph, t, io, c->stream);
+  if (e == hipSuccess && diag) {
+    int is_max[16] = {0};
+    is_max[LBM_DIAG_MAX_UF] = 1;
+    e = launch_finalize(c->partials, t.blocks, 16, is_max, diag, false, c->stream);
+  }
+  return from_hip(e);
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, float* f) {
+  if (!c || !f) return LBM_EINVAL;
+  return from_hip(launch_get_populations(c->storage, c->g, c->ph, c->links, c->buf[c->t & 1], f, c->stream));
+}
+
+lbm_status lbm_set_populations(lbm_ctx* c, const float* f) {
+  if (!c || !f) return LBM_EINVAL;
+  return from_hip(launch_set_populations(c->storage, c->g, c->ph, c->links, f, c->buf[c->t & 1], c->stream));
+}
+
+int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+lbm_status lbm_set_time(lbm_ctx* c, int64_t t) {
+  if (!c || t < 0) return LBM_EINVAL;
+  c->t = t;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_tiling(lbm_ctx* c, int32_t rows, int32_t zchunk) {
+  if (!c || (rows != 4 && rows != 8) || zchunk < 0) return LBM_EINVAL;
+  c->rows = rows;
+  c->zchunk = zchunk;
+  return LBM_OK;
+}
+
+size_t lbm_adjoint_work_bytes(const lbm_ctx* c) {
+  if (!c) return 0;
+  const Tiling t = make_tiling(c->g, c->rows, c->zchunk);
+  const size_t fields = static_cast<size_t>(c->g.n) * 11 * sizeof(float);
+  const size_t parts = static_cast<size_t>(t.blocks > 0 ? t.blocks : 0) * 3 * sizeof(double);
+  return ((fields + 255) / 256) * 256 + parts;
+}
+
+lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, float* lam_out, void* work,
+                            size_t work_bytes, double* dparams, double* drho0) {
+  if (!c || !x_t || !lam_in || !lam_out || !work || !dparams) return LBM_EINVAL;
+  if (work_bytes < lbm_adjoint_work_bytes(c)) return LBM_EINVAL;
+  if (lam_in == lam_out || static_cast<const void*>(lam_in) == x_t || static_cast<const void*>(lam_out) == x_t)
+    return LBM_EINVAL;
+  if (c->storage != Storage::F32) return LBM_ENOTSUP;
+  const Tiling t = tiling(c);
+  if (t.blocks <= 0) return LBM_ENOTSUP;
+  float* m = static_cast<float*>(work);
+  float* sbar = m + 5 * c->g.n;
+  const size_t fields = static_cast<size_t>(c->g.n) * 11 * sizeof(float);
+  double* parts = reinterpret_cast<double*>(static_cast<char*>(work) + ((fields + 255) / 256) * 256);
+  MarchIO io;
+  io.src = x_t;
+  io.links = c->links;
+  io.lam = lam_in;
+  io.m = m;
+  io.sbar = sbar;
+  io.partials = parts;
+  hipError_t e = launch_march(Storage::F32, Mode::Adjoint, c->g, c->ph, t, io, c->stream);
+  if (e == hipSuccess) e = launch_finalize(parts, t.blocks, 3, nullptr, dparams, true, c->stream);
+  if (e == hipSuccess) e = launch_adjoint_gather(c->g, c->links, m, sbar, c->stream);
+  if (e == hipSuccess) e = launch_adjoint_stream(c->g, c->ph, c->links, lam_in, m, lam_out, drho0, c->stream);
+  return from_hip(e);
+}
+
+lbm_status lbm_adjoint_seed(lbm_ctx* c, const float* grad_rho, float* lam) {
+  if (!c || !grad_rho || !lam) return LBM_EINVAL;
+  return from_hip(launch_adjoint_seed(c->g, c->links, grad_rho, lam, c->stream));
+}
+
+lbm_status lbm_destroy(lbm_ctx* c) {
+  if (!c) return LBM_OK;
+  const hipError_t e = hipStreamSynchronize(c->stream);
+  if (c->links) (void)hipFree(c->links);
+  if (c->partials) (void)hipFree(c->partials);
+  delete c;
+  return from_hip(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,360 @@
+// One-thread-per-cell kernels around the fused march: initial state, wall
+// link masks, conversion between stored and pre-collision populations,
+// deterministic reduction of per-workgroup partial sums and the two
+// neighbour passes of the adjoint step.
+
+#include "launch.h"
+
+namespace lbm {
+
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ uint64_t wrap_u(long long v, long long n) {
+  long long r = v % n;
+  return static_cast<uint64_t>(r < 0 ? r + n : r);
+}
+
+struct Coord {
+  int x, y, z;
+};
+
+__device__ __forceinline__ Coord coord_of(uint64_t c, const Grid& g) {
+  Coord r;
+  r.z = static_cast<int>(c / g.nxy);
+  const uint64_t rem = c - static_cast<uint64_t>(r.z) * g.nxy;
+  r.y = static_cast<int>(rem / g.nx);
+  r.x = static_cast<int>(rem - static_cast<uint64_t>(r.y) * g.nx);
+  return r;
+}
+
+// Linear index of (x + dx, y + dy, z + dz) on the periodic box.
+__device__ __forceinline__ uint64_t shifted(const Coord& p, int dx, int dy, int dz, const Grid& g) {
+  const uint64_t x = wrap_u(p.x + dx, g.nx), y = wrap_u(p.y + dy, g.ny), z = wrap_u(p.z + dz, g.nz);
+  return (z * g.ny + y) * g.nx + x;
+}
+
+// Plane-major index of population (s, i) at cell (x, y, z) + (dx, dy, dz):
+// X[z][s][i][y][x], i.e. ((z * 2 + s) * 19 + i) * nx * ny + y * nx + x.
+__device__ __forceinline__ uint64_t pm_at(int s, int i, const Coord& p, int dx, int dy, int dz, const Grid& g) {
+  const uint64_t x = wrap_u(p.x + dx, g.nx), y = wrap_u(p.y + dy, g.ny), z = wrap_u(p.z + dz, g.nz);
+  return ((z * 2 + s) * Q + i) * g.nxy + y * g.nx + x;
+}
+
+// Canonical SoA index (s * 19 + i) * N + c of the FP32 population interface.
+__device__ __forceinline__ uint64_t soa(int s, int i, uint64_t c, const Grid& g) {
+  return static_cast<uint64_t>(s * Q + i) * g.n + c;
+}
+
+__device__ __forceinline__ float wshift(const Phys& ph, int s, int i) { return weight(i) * ph.shift[s]; }
+
+// links bit i: cell x - c_i is solid (bit 0: x itself is solid).
+__global__ void links_kernel(const Grid g, const uint8_t* __restrict__ solid, uint32_t* __restrict__ links) {
+  for (uint64_t c = blockIdx.x * static_cast<uint64_t>(TPB) + threadIdx.x; c < g.n;
+       c += static_cast<uint64_t>(gridDim.x) * TPB) {
+    const Coord p = coord_of(c, g);
+    uint32_t bits = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      if (solid[shifted(p, -CX[i], -CY[i], -CZ[i], g)]) bits |= 1u << i;
+    links[c] = bits;
+  }
+}
+
+__device__ __forceinline__ bool is_solid(const uint32_t* links, uint64_t c) { return links && (links[c] & 1u); }
+// Neighbour x + c_i is solid: bit opp(i) of x.
+__device__ __forceinline__ bool ahead_solid(const uint32_t* links, uint64_t c, int i) {
+  return links && ((links[c] >> opp(i)) & 1u);
+}
+
+// Stored state whose pull at every fluid cell is f_i = w_i rho0 (rest state).
+template <Storage S>
+__global__ void init_kernel(const Grid g, const Phys ph, const uint32_t* __restrict__ links,
+                            const double* __restrict__ rho0, typename StorageTraits<S>::T* __restrict__ dst) {
+  using Tr = StorageTraits<S>;
+  for (uint64_t c = blockIdx.x * static_cast<uint64_t>(TPB) + threadIdx.x; c < g.n;
+       c += static_cast<uint64_t>(gridDim.x) * TPB) {
+    const Coord p = coord_of(c, g);
+    const bool solid = is_solid(links, c);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        float v = 0.0f;
+        if (!solid) {
+          const uint64_t src = ahead_solid(links, c, i) ? c : shifted(p, CX[i], CY[i], CZ[i], g);
+          v = static_cast<float>(weight_d(i) * rho0[s * g.n + src]);
+        }
+        if constexpr (Tr::shifted) v -= wshift(ph, s, i);
+        dst[pm_at(s, i, p, 0, 0, 0, g)] = Tr::encode(v);
+      }
+    }
+  }
+}
+
+template <Storage S>
+__global__ void get_pop_kernel(const Grid g, const Phys ph, const uint32_t* __restrict__ links,
+                               const typename StorageTraits<S>::T* __restrict__ src, float* __restrict__ f) {
+  using Tr = StorageTraits<S>;
+  for (uint64_t c = blockIdx.x * static_cast<uint64_t>(TPB) + threadIdx.x; c < g.n;
+       c += static_cast<uint64_t>(gridDim.x) * TPB) {
+    const Coord p = coord_of(c, g);
+    const bool solid = is_solid(links, c);
+    const uint32_t lk = links ? links[c] : 0u;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        float v = 0.0f;
+        if (!solid) {
+          const bool bb = (i != 0) && ((lk >> i) & 1u);
+          const uint64_t at = bb ? pm_at(s, opp(i), p, 0, 0, 0, g) : pm_at(s, i, p, -CX[i], -CY[i], -CZ[i], g);
+          v = Tr::decode(src[at]);
+          if constexpr (Tr::shifted) v += wshift(ph, s, i);
+        }
+        f[soa(s, i, c, g)] = v;
+      }
+    }
+  }
+}
+
+template <Storage S>
+__global__ void set_pop_kernel(const Grid g, const Phys ph, const uint32_t* __restrict__ links,
+                               const float* __restrict__ f, typename StorageTraits<S>::T* __restrict__ dst) {
+  using Tr = StorageTraits<S>;
+  for (uint64_t c = blockIdx.x * static_cast<uint64_t>(TPB) + threadIdx.x; c < g.n;
+       c += static_cast<uint64_t>(gridDim.x) * TPB) {
+    const Coord p = coord_of(c, g);
+    const bool solid = is_solid(links, c);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        float v = 0.0f;
+        if (!solid) {
+          // X_j(y) is read by f_j(y + c_j), or by f_opp(j)(y) if y + c_j is a wall.
+          const bool back = ahead_solid(links, c, j);
+          const uint64_t at = back ? c : shifted(p, CX[j], CY[j], CZ[j], g);
+          const int pop = back ? opp(j) : j;
+          v = f[soa(s, pop, at, g)];
+        }
+        if constexpr (Tr::shifted) v -= wshift(ph, s, j);
+        dst[pm_at(s, j, p, 0, 0, 0, g)] = Tr::encode(v);
+      }
+    }
+  }
+}
+
+// Sum (or max) of per-workgroup partials, one value per block of threads,
+// in a fixed order so that results are bitwise reproducible.
+__global__ void finalize_kernel(const double* __restrict__ partials, int blocks, int nvals,
+                                const int* __restrict__ is_max_dev, int max_index, double* out,
+                                int accumulate) {
+  __shared__ double sh[TPB];
+  const int k = blockIdx.x;
+  const bool mx = (k == max_index);
+  double acc = mx ? 0.0 : 0.0;
+  for (int b = threadIdx.x; b < blocks; b += TPB) {
+    const double v = partials[static_cast<uint64_t>(b) * nvals + k];
+    acc = mx ? fmax(acc, v) : acc + v;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = TPB / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] = mx ? fmax(sh[threadIdx.x], sh[threadIdx.x + o])
+                                              : sh[threadIdx.x] + sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = accumulate ? out[k] + sh[0] : sh[0];
+  (void)is_max_dev;
+}
+
+// Adjoint, pass 2: A^b(x) = a^b(x) + sum_i w_i c_i . Sbar^b(x - c_i) on fluid x.
+// m holds (a^A, a^B, b_x, b_y, b_z) per cell; a^b is replaced by A^b in place.
+__global__ void adjoint_gather_kernel(const Grid g, const uint32_t* __restrict__ links, float* __restrict__ m,
+                                      const float* __restrict__ sbar) {
+  for (uint64_t c = blockIdx.x * static_cast<uint64_t>(TPB) + threadIdx.x; c < g.n;
+       c += static_cast<uint64_t>(gridDim.x) * TPB) {
+    if (is_solid(links, c)) continue;
+    const Coord p = coord_of(c, g);
+    float r[2] = {0.f, 0.f};
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const uint64_t at = shifted(p, -CX[i], -CY[i], -CZ[i], g);
+      const float w = weight(i);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const float* sb = sbar + static_cast<uint64_t>(3 * s) * g.n;
+        r[s] += w * (CX[i] * sb[at] + CY[i] * sb[g.n + at] + CZ[i] * sb[2 * g.n + at]);
+      }
+    }
+    m[c] += r[0];
+    m[g.n + c] += r[1];
+  }
+}
+
+// Adjoint, pass 3 (transpose of the pull with bounce-back):
+//   lam_t,i(y) = fbar_k(x) with x = y + c_i, k = i, or x = y, k = opp(i) when
+//   y + c_i is a wall, and fbar_k(x) = (1 - w) lam_{t+1},k(x) + A(x) + b(x) . c_k.
+__global__ void adjoint_stream_kernel(const Grid g, const Phys ph, const uint32_t* __restrict__ links,
+                                      const float* __restrict__ lam_in, const float* __restrict__ m,
+                                      float* __restrict__ lam_out, double* __restrict__ drho0) {
+  for (uint64_t c = blockIdx.x * static_cast<uint64_t>(TPB) + threadIdx.x; c < g.n;
+       c += static_cast<uint64_t>(gridDim.x) * TPB) {
+    const bool solid = is_solid(links, c);
+    const Coord p = coord_of(c, g);
+    const uint32_t lk = links ? links[c] : 0u;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const float keep = 1.0f - ph.omega[s];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        float v = 0.0f;
+        if (!solid) {
+          const bool back = (i != 0) && ((lk >> opp(i)) & 1u);
+          const uint64_t x = back ? c : shifted(p, CX[i], CY[i], CZ[i], g);
+          const uint64_t lx = back ? pm_at(s, opp(i), p, 0, 0, 0, g) : pm_at(s, i, p, CX[i], CY[i], CZ[i], g);
+          // b . c_k with c_k = c_i, or -c_i after a bounce
+          float bc = 0.0f;
+          if (i != 0) {
+            const float dot = CX[i] * m[2 * g.n + x] + CY[i] * m[3 * g.n + x] + CZ[i] * m[4 * g.n + x];
+            bc = back ? -dot : dot;
+          }
+          v = keep * lam_in[lx] + m[s * g.n + x] + bc;
+        }
+        lam_out[pm_at(s, i, p, 0, 0, 0, g)] = v;
+      }
+      if (drho0) {
+        double d = 0.0;
+        if (!solid) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int i = 0; i < Q; ++i) acc += weight(i) * lam_in[pm_at(s, i, p, 0, 0, 0, g)];
+          d = static_cast<double>(keep * acc + m[s * g.n + c]);
+        }
+        drho0[s * g.n + c] = d;
+      }
+    }
+  }
+}
+
+// dL/dX_T for L(rho(T)): lam_i(y) = grad(y + c_i), or grad(y) if y + c_i is a wall.
+__global__ void adjoint_seed_kernel(const Grid g, const uint32_t* __restrict__ links,
+                                    const float* __restrict__ grad, float* __restrict__ lam) {
+  for (uint64_t c = blockIdx.x * static_cast<uint64_t>(TPB) + threadIdx.x; c < g.n;
+       c += static_cast<uint64_t>(gridDim.x) * TPB) {
+    const bool solid = is_solid(links, c);
+    const Coord p = coord_of(c, g);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        float v = 0.0f;
+        if (!solid) {
+          const uint64_t x = ahead_solid(links, c, i) ? c : shifted(p, CX[i], CY[i], CZ[i], g);
+          v = grad[s * g.n + x];
+        }
+        lam[pm_at(s, i, p, 0, 0, 0, g)] = v;
+      }
+    }
+  }
+}
+
+unsigned grid_for(uint64_t n) {
+  uint64_t b = (n + TPB - 1) / TPB;
+  if (b > 65536ull * 16) b = 65536ull * 16;
+  if (b == 0) b = 1;
+  return static_cast<unsigned>(b);
+}
+
+}  // namespace
+
+hipError_t launch_links(const Grid& g, const uint8_t* solid, uint32_t* links, hipStream_t st) {
+  hipLaunchKernelGGL(links_kernel, dim3(grid_for(g.n)), dim3(TPB), 0, st, g, solid, links);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(Storage s, const Grid& g, const Phys& ph, const uint32_t* links, const double* rho0,
+                       void* dst, hipStream_t st) {
+  const dim3 gr(grid_for(g.n)), bl(TPB);
+  switch (s) {
+    case Storage::F32:
+      hipLaunchKernelGGL(init_kernel<Storage::F32>, gr, bl, 0, st, g, ph, links, rho0, static_cast<float*>(dst));
+      break;
+    case Storage::F16:
+      hipLaunchKernelGGL(init_kernel<Storage::F16>, gr, bl, 0, st, g, ph, links, rho0, static_cast<_Float16*>(dst));
+      break;
+    case Storage::BF16:
+      hipLaunchKernelGGL(init_kernel<Storage::BF16>, gr, bl, 0, st, g, ph, links, rho0, static_cast<uint16_t*>(dst));
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_get_populations(Storage s, const Grid& g, const Phys& ph, const uint32_t* links,
+                                  const void* src, float* f, hipStream_t st) {
+  const dim3 gr(grid_for(g.n)), bl(TPB);
+  switch (s) {
+    case Storage::F32:
+      hipLaunchKernelGGL(get_pop_kernel<Storage::F32>, gr, bl, 0, st, g, ph, links, static_cast<const float*>(src), f);
+      break;
+    case Storage::F16:
+      hipLaunchKernelGGL(get_pop_kernel<Storage::F16>, gr, bl, 0, st, g, ph, links, static_cast<const _Float16*>(src), f);
+      break;
+    case Storage::BF16:
+      hipLaunchKernelGGL(get_pop_kernel<Storage::BF16>, gr, bl, 0, st, g, ph, links, static_cast<const uint16_t*>(src), f);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_set_populations(Storage s, const Grid& g, const Phys& ph, const uint32_t* links,
+                                  const float* f, void* dst, hipStream_t st) {
+  const dim3 gr(grid_for(g.n)), bl(TPB);
+  switch (s) {
+    case Storage::F32:
+      hipLaunchKernelGGL(set_pop_kernel<Storage::F32>, gr, bl, 0, st, g, ph, links, f, static_cast<float*>(dst));
+      break;
+    case Storage::F16:
+      hipLaunchKernelGGL(set_pop_kernel<Storage::F16>, gr, bl, 0, st, g, ph, links, f, static_cast<_Float16*>(dst));
+      break;
+    case Storage::BF16:
+      hipLaunchKernelGGL(set_pop_kernel<Storage::BF16>, gr, bl, 0, st, g, ph, links, f, static_cast<uint16_t*>(dst));
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* partials, int blocks, int nvals, const int* is_max, double* out,
+                           bool accumulate, hipStream_t st) {
+  // is_max on the host: the index of the (single) max entry, or -1.
+  int max_index = -1;
+  if (is_max)
+    for (int k = 0; k < nvals; ++k)
+      if (is_max[k]) max_index = k;
+  hipLaunchKernelGGL(finalize_kernel, dim3(nvals), dim3(TPB), 0, st, partials, blocks, nvals,
+                     static_cast<const int*>(nullptr), max_index, out, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_gather(const Grid& g, const uint32_t* links, float* m, const float* sbar,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(adjoint_gather_kernel, dim3(grid_for(g.n)), dim3(TPB), 0, st, g, links, m, sbar);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_stream(const Grid& g, const Phys& ph, const uint32_t* links, const float* lam_in,
+                                 const float* m, float* lam_out, double* drho0, hipStream_t st) {
+  hipLaunchKernelGGL(adjoint_stream_kernel, dim3(grid_for(g.n)), dim3(TPB), 0, st, g, ph, links, lam_in, m,
+                     lam_out, drho0);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_seed(const Grid& g, const uint32_t* links, const float* grad_rho, float* lam,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(adjoint_seed_kernel, dim3(grid_for(g.n)), dim3(TPB), 0, st, g, links, grad_rho, lam);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

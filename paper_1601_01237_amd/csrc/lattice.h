@@ -1,0 +1,68 @@
+// D3Q19 velocity set and the storage forms of the population buffers.
+//
+// Velocities follow the lattice of Sec. 2 of arXiv 1601.01237 (19 discrete
+// velocities); the weights are the isotropic ones (1/3 rest, 1/18 faces,
+// 1/36 edges).  Order: rest, then opposite pairs (1,2), (3,4), ..., (17,18),
+// so that direction 2k-1 and 2k are negatives of each other.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int Q = 19;
+
+// Component tables (x, y, z) of each direction.
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+constexpr float W0 = 1.0f / 3.0f;
+constexpr float WF = 1.0f / 18.0f;
+constexpr float WE = 1.0f / 36.0f;
+
+__host__ __device__ constexpr float weight(int i) { return i == 0 ? W0 : (i <= 6 ? WF : WE); }
+__host__ __device__ constexpr double weight_d(int i) {
+  return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// ---------------------------------------------------------------------------
+// Storage forms.  Arithmetic is FP32; the 16-bit forms hold X - w_i rho_shift
+// rounded to nearest even.
+// ---------------------------------------------------------------------------
+enum class Storage : int { F32 = 0, F16 = 1, BF16 = 2 };
+
+template <Storage S> struct StorageTraits;
+
+template <> struct StorageTraits<Storage::F32> {
+  using T = float;
+  static constexpr bool shifted = false;
+  __device__ static inline float decode(float v) { return v; }
+  __device__ static inline float encode(float v) { return v; }
+};
+
+template <> struct StorageTraits<Storage::F16> {
+  using T = _Float16;
+  static constexpr bool shifted = true;
+  __device__ static inline float decode(_Float16 v) { return static_cast<float>(v); }
+  __device__ static inline _Float16 encode(float v) { return static_cast<_Float16>(v); }
+};
+
+// bfloat16 kept as its bit pattern: the upper half of an IEEE binary32.
+template <> struct StorageTraits<Storage::BF16> {
+  using T = uint16_t;
+  static constexpr bool shifted = true;
+  __device__ static inline float decode(uint16_t v) {
+    return __uint_as_float(static_cast<uint32_t>(v) << 16);
+  }
+  // Round to nearest, ties to even, on the 16 discarded mantissa bits.
+  __device__ static inline uint16_t encode(float v) {
+    uint32_t b = __float_as_uint(v);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return static_cast<uint16_t>(b >> 16);
+  }
+};
+
+}  // namespace lbm

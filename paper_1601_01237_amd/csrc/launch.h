@@ -1,0 +1,76 @@
+// Host-side launchers of the device kernels (C++ linkage, internal to liblbm).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.h"
+
+namespace lbm {
+
+// Per-launch description of the grid and the physics, shared by every kernel.
+struct Grid {
+  int nx, ny, nz;
+  uint32_t nxy;  // nx * ny
+  uint64_t n;    // nx * ny * nz
+};
+
+struct Phys {
+  float omega[2];     // 1 / tau_a
+  float g_ab, g_ba;   // G^{AB}, G^{BA}
+  float rho_wall[2];  // rho_s^a
+  float shift[2];     // rho_shift^a of the 16-bit storage forms (0 for FP32)
+};
+
+struct Tiling {
+  int rows;      // 4 or 8 rows of 64 cells per workgroup
+  int zchunk;    // z planes marched per workgroup
+  int tiles_x, tiles_y, tiles_z;
+  int blocks;
+};
+
+Tiling make_tiling(const Grid& g, int rows, int zchunk);
+
+// Diagnostic region (device-side floats).
+struct Region {
+  float cx, cy, cz;
+  float r_in2, r_out2, thr;
+  float p_g;  // symmetric coupling used in the pressure
+};
+
+enum class Mode : int { Step = 0, Moments = 1, Adjoint = 2 };
+
+struct MarchIO {
+  const void* src = nullptr;       // stored state X_t
+  void* dst = nullptr;             // Step: X_{t+1}
+  const uint32_t* links = nullptr; // wall link bits or null
+  float* rho_out = nullptr;        // Moments
+  float* uf_out = nullptr;         // Moments
+  double* partials = nullptr;      // Moments (16 per block) / Adjoint (3 per block)
+  Region region{};
+  const float* lam = nullptr;      // Adjoint: lam_{t+1}
+  float* m = nullptr;              // Adjoint: 5 N  (a^A, a^B, b_x, b_y, b_z)
+  float* sbar = nullptr;           // Adjoint: 6 N  (Sbar^A xyz, Sbar^B xyz)
+};
+
+hipError_t launch_march(Storage s, Mode mode, const Grid& g, const Phys& ph, const Tiling& t,
+                        const MarchIO& io, hipStream_t st);
+
+hipError_t launch_init(Storage s, const Grid& g, const Phys& ph, const uint32_t* links,
+                       const double* rho0, void* dst, hipStream_t st);
+hipError_t launch_links(const Grid& g, const uint8_t* solid, uint32_t* links, hipStream_t st);
+hipError_t launch_get_populations(Storage s, const Grid& g, const Phys& ph, const uint32_t* links,
+                                  const void* src, float* f, hipStream_t st);
+hipError_t launch_set_populations(Storage s, const Grid& g, const Phys& ph, const uint32_t* links,
+                                  const float* f, void* dst, hipStream_t st);
+hipError_t launch_finalize(const double* partials, int blocks, int nvals, const int* is_max,
+                           double* out, bool accumulate, hipStream_t st);
+hipError_t launch_adjoint_gather(const Grid& g, const uint32_t* links, float* m, const float* sbar,
+                                 hipStream_t st);
+hipError_t launch_adjoint_stream(const Grid& g, const Phys& ph, const uint32_t* links,
+                                 const float* lam_in, const float* m, float* lam_out,
+                                 double* drho0, hipStream_t st);
+hipError_t launch_adjoint_seed(const Grid& g, const uint32_t* links, const float* grad_rho,
+                               float* lam, hipStream_t st);
+
+}  // namespace lbm

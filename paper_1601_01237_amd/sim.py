@@ -1,0 +1,175 @@
+"""``Sim``: one two-component D3Q19 run on one GPU through the C ABI.
+
+PyTorch only owns the device memory and supplies the stream; the step,
+moments, population transfers and adjoint run in liblbm.so.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+
+STORAGE = {"fp32": (_lib.FP32, torch.float32), "fp16": (_lib.FP16, torch.float16),
+           "bf16": (_lib.BF16, torch.bfloat16)}
+
+DIAG_NAMES = ["mass_a", "mass_b", "mom_x", "mom_y", "mom_z", "max_uf", "nonfinite", "n_fluid",
+              "p_in_sum", "n_in", "p_out_sum", "n_out", "n_thr", "sdx_thr", "sdy_thr", "sdz_thr"]
+
+Q = _lib.Q
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def coupling_matrix(G):
+    """G as a 2x2 matrix; a scalar means G^{AB} = G^{BA} = G and G^{aa} = 0."""
+    if np.isscalar(G):
+        return ((0.0, float(G)), (float(G), 0.0))
+    return tuple(tuple(float(v) for v in row) for row in G)
+
+
+class Sim:
+    """A context of liblbm plus the two state buffers it ping-pongs between.
+
+    Parameters
+    ----------
+    rho0 : array (2, nz, ny, nx)  initial species densities (float64).
+    tau : (tau_A, tau_B) relaxation times (Eq. 2).
+    G : scalar or 2x2 coupling of Eq. (7) (paper sign: repulsion < 0).
+    storage : "fp32", "fp16" or "bf16" (16-bit forms store f - w rho_shift).
+    rho_shift : per-species shift of the 16-bit forms; default: mean density.
+    solid : optional bool array (nz, ny, nx) of wall cells.
+    rho_wall : wall potential rho_s^a (Sec. 4).
+    """
+
+    def __init__(self, rho0, tau=(1.0, 1.0), G=-1.0, storage="fp32", rho_shift=None,
+                 solid=None, rho_wall=(0.0, 0.0), device="cuda:0", rows=None, zchunk=None):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        rho0 = torch.as_tensor(np.asarray(rho0, dtype=np.float64))
+        if rho0.ndim != 4 or rho0.shape[0] != 2:
+            raise ValueError("rho0 must have shape (2, nz, ny, nx)")
+        self.shape = tuple(int(v) for v in rho0.shape[1:])
+        nz, ny, nx = self.shape
+        self.n = nx * ny * nz
+        self.storage = storage
+        code, self.dtype = STORAGE[storage]
+        fluid = np.ones(self.shape, bool) if solid is None else ~np.asarray(solid, bool)
+        if rho_shift is None:
+            r = rho0.numpy()
+            rho_shift = tuple(float(r[a][fluid].mean()) for a in range(2)) if storage != "fp32" else (0.0, 0.0)
+        self.rho_shift = tuple(float(v) for v in rho_shift)
+        self.G = coupling_matrix(G)
+        self.tau = tuple(float(t) for t in (tau if not np.isscalar(tau) else (tau, tau)))
+        self.rho_wall = tuple(float(v) for v in rho_wall)
+
+        p = _lib.Params()
+        p.nx, p.ny, p.nz = nx, ny, nz
+        p.storage = code
+        p.tau[0], p.tau[1] = self.tau
+        for a in range(2):
+            for b in range(2):
+                p.G[a][b] = self.G[a][b]
+        p.rho_shift[0], p.rho_shift[1] = self.rho_shift
+        p.rho_wall[0], p.rho_wall[1] = self.rho_wall
+        self.params = p
+
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.bufs = [torch.empty(2 * Q * self.n, dtype=self.dtype, device=self.device) for _ in range(2)]
+            self.rho0_dev = rho0.to(self.device).contiguous()
+            self.solid_dev = None
+            if solid is not None:
+                self.solid_dev = torch.as_tensor(np.asarray(solid, dtype=np.uint8)).to(self.device).contiguous()
+            ctx = C.c_void_p()
+            _lib.check("lbm_init", self.lib.lbm_init(
+                C.byref(ctx), C.byref(p), _ptr(self.bufs[0]), _ptr(self.bufs[1]),
+                _ptr(self.solid_dev), _ptr(self.rho0_dev), C.c_void_p(self.stream.cuda_stream)))
+        self.ctx = ctx
+        if rows is not None or zchunk is not None:
+            self.set_tiling(rows or 8, zchunk or 0)
+
+    # -- lifetime --------------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None):
+            _lib.check("lbm_destroy", self.lib.lbm_destroy(self.ctx))
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- stepping --------------------------------------------------------------
+    @property
+    def t(self):
+        return int(self.lib.lbm_time(self.ctx))
+
+    def set_time(self, t):
+        _lib.check("lbm_set_time", self.lib.lbm_set_time(self.ctx, int(t)))
+
+    def step(self, n=1):
+        _lib.check("lbm_step", self.lib.lbm_step(self.ctx, int(n)))
+
+    def set_tiling(self, rows=8, zchunk=0):
+        _lib.check("lbm_set_tiling", self.lib.lbm_set_tiling(self.ctx, int(rows), int(zchunk)))
+
+    @property
+    def state(self):
+        """The stored (post-collision) buffer of the current time level."""
+        return self.bufs[self.t & 1]
+
+    # -- observables -------------------------------------------------------------
+    def moments(self, region=None, want_fields=True):
+        """(rho (2,nz,ny,nx), u_F (3,nz,ny,nx), diag dict) at the current time."""
+        nz, ny, nx = self.shape
+        rho = uf = None
+        if want_fields:
+            rho = torch.empty(2 * self.n, dtype=torch.float32, device=self.device)
+            uf = torch.empty(3 * self.n, dtype=torch.float32, device=self.device)
+        diag = torch.empty(_lib.DIAG_LEN, dtype=torch.float64, device=self.device)
+        reg = None
+        if region is not None:
+            reg = _lib.DiagRegion()
+            c = region.get("center", (nx / 2.0, ny / 2.0, nz / 2.0))
+            reg.center[0], reg.center[1], reg.center[2] = c
+            reg.r_in = region.get("r_in", 0.0)
+            reg.r_out = region.get("r_out", 1e30)
+            reg.thr = region.get("thr", 0.515)
+        _lib.check("lbm_moments", self.lib.lbm_moments(
+            self.ctx, _ptr(rho), _ptr(uf), _ptr(diag), C.byref(reg) if reg is not None else None))
+        d = diag.cpu().numpy()
+        out = dict(zip(DIAG_NAMES, d.tolist()))
+        out["vector"] = d
+        if want_fields:
+            return rho.view(2, nz, ny, nx), uf.view(3, nz, ny, nx), out
+        return None, None, out
+
+    def populations(self):
+        """Pre-collision populations f_i^a(x, t) as FP32 (2, 19, nz, ny, nx)."""
+        f = torch.empty(2 * Q * self.n, dtype=torch.float32, device=self.device)
+        _lib.check("lbm_get_populations", self.lib.lbm_get_populations(self.ctx, _ptr(f)))
+        return f.view(2, Q, *self.shape)
+
+    def set_populations(self, f):
+        f = torch.as_tensor(f, dtype=torch.float32).to(self.device).contiguous()
+        if f.numel() != 2 * Q * self.n:
+            raise ValueError("populations must have 2*19*N elements")
+        _lib.check("lbm_set_populations", self.lib.lbm_set_populations(self.ctx, _ptr(f)))
+        self.stream.synchronize()
+
+    # -- checkpoint / resume -----------------------------------------------------
+    def checkpoint(self):
+        """Copy of (stored state, t) that :meth:`restore` can put back."""
+        return self.state.clone(), self.t
+
+    def restore(self, ckpt):
+        buf, t = ckpt
+        self.bufs[t & 1].copy_(buf)
+        self.set_time(t)

@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+declared in include/lbm.h, and its velocity set is the oracle's D3Q19."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import lbm as olbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+LIB = os.path.join(ROOT, "paper_1601_01237_amd", "liblbm.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("liblbm.so is not built (run __graft_entry__.build())")
+    from paper_1601_01237_amd import _lib
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "lbm_step" in names and "lbm_adjoint_step" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_1601_01237_amd import _lib
+    assert sorted(_lib.EXPORTED) == names
+
+
+def test_velocity_set_matches_oracle(lib):
+    from paper_1601_01237_amd import _lib
+    c, w = _lib.velocity_set()
+    np.testing.assert_array_equal(np.array(c), olbm.C)
+    np.testing.assert_allclose(np.array(w), olbm.W, rtol=0, atol=0)
+
+
+def test_status_strings(lib):
+    lib.lbm_status_str.restype = ctypes.c_char_p
+    assert lib.lbm_status_str(0) == b"ok"
+    assert lib.lbm_status_str(-5) == b"not supported"
+
+
+def test_null_arguments_are_rejected_without_a_gpu(lib):
+    from paper_1601_01237_amd import _lib
+    ctx = ctypes.c_void_p()
+    p = _lib.Params()
+    # null buffers -> invalid argument, checked before any HIP call
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), None, None, None, None, None) == -1
+    assert lib.lbm_step(None, 1) == -1
+    assert lib.lbm_moments(None, None, None, None, None) == -1
+    assert lib.lbm_destroy(None) == 0
+    assert lib.lbm_time(None) == -1
+
+
+def test_parameter_checks_without_a_gpu(lib):
+    from paper_1601_01237_amd import _lib
+    ctx = ctypes.c_void_p()
+    p = _lib.Params()
+    p.nx, p.ny, p.nz = 4, 4, 4
+    p.tau[0], p.tau[1] = 1.0, 1.0
+    dummy_a, dummy_b, dummy_r = ctypes.c_void_p(16), ctypes.c_void_p(32), ctypes.c_void_p(48)
+    # G^{AA} != 0 is outside the model of the paper (Sec. 2): not supported
+    p.G[0][0] = 0.5
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), dummy_a, dummy_b, None, dummy_r, None) == -5
+    p.G[0][0] = 0.0
+    # tau <= 1/2 is invalid (negative viscosity)
+    p.tau[1] = 0.5
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), dummy_a, dummy_b, None, dummy_r, None) == -1
+    p.tau[1] = 1.0
+    p.storage = 7
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), dummy_a, dummy_b, None, dummy_r, None) == -1
+    p.storage = 0
+    p.nx = 0
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), dummy_a, dummy_b, None, dummy_r, None) == -1
+    p.nx = 4
+    # same buffer twice
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), dummy_a, dummy_a, None, dummy_r, None) == -1
+    # population arrays beyond 32-bit offsets are refused
+    p.nx, p.ny, p.nz = 2048, 1024, 1024
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), dummy_a, dummy_b, None, dummy_r, None) == -5
