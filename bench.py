@@ -73,12 +73,12 @@ def time_steps(sim, steps, warmup):
     return start.elapsed_time(end) / steps  # ms per step (= per launch)
 
 
-def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1.0, rows=None, zchunk=None):
+def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1.0, tile=None, zchunk=None):
     from paper_1601_01237_amd import inputs
     from paper_1601_01237_amd.sim import Sim
     if rho0 is None:
         rho0 = inputs.sphere_droplet(shape, radius=shape[0] / 8.0, seed=0)
-    sim = Sim(rho0, tau=(tau, tau), G=G, storage=storage, solid=solid, rows=rows, zchunk=zchunk)
+    sim = Sim(rho0, tau=(tau, tau), G=G, storage=storage, solid=solid, tile=tile, zchunk=zchunk)
     ms = time_steps(sim, steps, warmup)
     _, _, diag = sim.moments(want_fields=False)
     n = int(np.prod(shape))
@@ -86,6 +86,33 @@ def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1
     mlups = n / (ms * 1e-3) / 1e6
     gbs = BYTES_PER_CELL[storage] * n / (ms * 1e-3) / 1e9
     return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, nonfinite=diag["nonfinite"], n=n)
+
+
+def copy_ceiling(gib=2.0, reps=10):
+    """Read + write bandwidth of the library's plain streaming copy (GB/s)."""
+    import ctypes
+    import torch
+    from paper_1601_01237_amd import _lib
+    lib = _lib.load()
+    n = int(gib * (1 << 30))
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    h = ctypes.c_void_p(stream.cuda_stream)
+    for _ in range(2):
+        _lib.check("lbm_stream_copy", lib.lbm_stream_copy(ctypes.c_void_p(src.data_ptr()),
+                                                           ctypes.c_void_p(dst.data_ptr()), n, h))
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        _lib.check("lbm_stream_copy", lib.lbm_stream_copy(ctypes.c_void_p(src.data_ptr()),
+                                                           ctypes.c_void_p(dst.data_ptr()), n, h))
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / reps
+    del src, dst
+    return 2.0 * n / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(shape, seconds_budget=30.0):
@@ -141,6 +168,8 @@ def main():
     traffic = stored_traffic(workload, "fp32")
 
     extra = {}
+    print("[bench] copy ceiling", file=sys.stderr, flush=True)
+    ceiling = copy_ceiling()
     if not args.no_extra:
         steps_big = max(10, args.steps // 10)
         big = (512, 512, 512)
@@ -181,6 +210,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_cell": BYTES_PER_CELL["fp32"],
+                     "copy_ceiling_gbs": round(ceiling, 1),
+                     "frac_of_copy_ceiling": round(achieved / ceiling, 4),
                      "kernel": "march_kernel<F32, no walls, Step, 8 rows>"},
         "cpu_baseline": cpu,
         "extra": extra,

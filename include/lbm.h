@@ -169,10 +169,12 @@ int64_t lbm_time(const lbm_ctx *ctx);
 /* Sets t (e.g. after restoring a checkpoint into the matching buffer). */
 lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
 
-/* Tiling of the fused kernels: rows of cells per workgroup (4 or 8) and
- * z planes marched per workgroup (>= 1; 0 picks a default from the grid).
- * Results do not depend on this choice (bitwise).  Host-side setting. */
-lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t rows, int32_t zchunk);
+/* Tiling of the fused step kernel: workgroup tile shape and the number of z
+ * planes each workgroup marches through (>= 1; 0 picks a default from the
+ * grid).  Shapes (cells in x by y): 0 = 64x8 (default), 1 = 64x12,
+ * 2 = 32x16, 3 = 32x24, 4 = 64x4.  Results do not depend on this choice
+ * (bitwise).  Host-side setting; diagnostics and the adjoint use shape 0. */
+lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t tile, int32_t zchunk);
 
 /* ---- Adjoint (reverse mode) of one step, FP32 storage only ------------
  * Let X_t be the stored state at t and L a scalar objective.  With
@@ -197,6 +199,13 @@ lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *x_t, const float *lam_in,
  * grad_rho (device float, 2*N, index a*N + c) = dL/drho^a(x, T), writes lam
  * (device float, 2*19*N, plane-major) = dL/dX_T.  Solid cells get zero. */
 lbm_status lbm_adjoint_seed(lbm_ctx *ctx, const float *grad_rho, float *lam);
+
+/* Plain device-to-device copy of `bytes` bytes (a multiple of 16; both
+ * pointers 16-byte aligned, not overlapping) on `stream` (hipStream_t as
+ * void*).  Not part of the method: it is the reference for the read + write
+ * bandwidth the memory system delivers to a streaming kernel, against which
+ * the step kernel's bandwidth is compared. */
+lbm_status lbm_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Frees the context and what the library allocated; NULL is a no-op.
  * Waits for the context's stream first. */

@@ -27,6 +27,9 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-Wall",
+    # no implicit multiply-add fusion: every instance of a kernel template
+    # rounds identically (fused operations are written out with fmaf)
+    "-ffp-contract=off",
     # packed FP32 VALU forms are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE,

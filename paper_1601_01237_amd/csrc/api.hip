@@ -21,7 +21,7 @@ struct lbm_ctx {
   uint32_t* links;     // owned; null without walls
   hipStream_t stream;
   int64_t t;
-  int rows, zchunk;
+  int tile, zchunk;    // tiling of the step kernel
   double* partials;    // owned reduction scratch
   size_t partials_cap; // doubles
 };
@@ -32,7 +32,9 @@ size_t elem_size(Storage s) { return s == Storage::F32 ? 4 : 2; }
 
 lbm_status from_hip(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 
-Tiling tiling(const lbm_ctx* c) { return make_tiling(c->g, c->rows, c->zchunk); }
+// Step kernel: the selected tile shape; diagnostics and adjoint: shape 0.
+Tiling step_tiling(const lbm_ctx* c) { return make_tiling(c->g, c->tile, c->zchunk); }
+Tiling aux_tiling(const lbm_ctx* c) { return make_tiling(c->g, 0, 0); }
 
 lbm_status ensure_partials(lbm_ctx* c, size_t need) {
   if (need <= c->partials_cap) return LBM_OK;
@@ -118,7 +120,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
   c->links = nullptr;
   c->stream = static_cast<hipStream_t>(stream);
   c->t = 0;
-  c->rows = 8;
+  c->tile = 0;
   c->zchunk = 0;
   c->partials = nullptr;
   c->partials_cap = 0;
@@ -147,7 +149,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
 
 lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   if (!c || n < 0) return LBM_EINVAL;
-  const Tiling t = tiling(c);
+  const Tiling t = step_tiling(c);
   if (t.blocks <= 0) return LBM_ENOTSUP;
   for (int64_t k = 0; k < n; ++k) {
     MarchIO io;
@@ -163,7 +165,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
 
 lbm_status lbm_moments(lbm_ctx* c, float* rho, float* u_f, double* diag, const lbm_diag_region* region) {
   if (!c) return LBM_EINVAL;
-  const Tiling t = tiling(c);
+  const Tiling t = aux_tiling(c);
   if (t.blocks <= 0) return LBM_ENOTSUP;
   if (diag) {
     const lbm_status s = ensure_partials(c, static_cast<size_t>(t.blocks) * 16);
@@ -226,16 +228,16 @@ lbm_status lbm_set_time(lbm_ctx* c, int64_t t) {
   return LBM_OK;
 }
 
-lbm_status lbm_set_tiling(lbm_ctx* c, int32_t rows, int32_t zchunk) {
-  if (!c || (rows != 4 && rows != 8) || zchunk < 0) return LBM_EINVAL;
-  c->rows = rows;
+lbm_status lbm_set_tiling(lbm_ctx* c, int32_t tile, int32_t zchunk) {
+  if (!c || tile < 0 || tile >= TILE_SHAPES || zchunk < 0) return LBM_EINVAL;
+  c->tile = tile;
   c->zchunk = zchunk;
   return LBM_OK;
 }
 
 size_t lbm_adjoint_work_bytes(const lbm_ctx* c) {
   if (!c) return 0;
-  const Tiling t = make_tiling(c->g, c->rows, c->zchunk);
+  const Tiling t = aux_tiling(c);
   const size_t fields = static_cast<size_t>(c->g.n) * 11 * sizeof(float);
   const size_t parts = static_cast<size_t>(t.blocks > 0 ? t.blocks : 0) * 3 * sizeof(double);
   return ((fields + 255) / 256) * 256 + parts;
@@ -248,7 +250,7 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, fl
   if (lam_in == lam_out || static_cast<const void*>(lam_in) == x_t || static_cast<const void*>(lam_out) == x_t)
     return LBM_EINVAL;
   if (c->storage != Storage::F32) return LBM_ENOTSUP;
-  const Tiling t = tiling(c);
+  const Tiling t = aux_tiling(c);
   if (t.blocks <= 0) return LBM_ENOTSUP;
   float* m = static_cast<float*>(work);
   float* sbar = m + 5 * c->g.n;
@@ -271,6 +273,12 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, fl
 lbm_status lbm_adjoint_seed(lbm_ctx* c, const float* grad_rho, float* lam) {
   if (!c || !grad_rho || !lam) return LBM_EINVAL;
   return from_hip(launch_adjoint_seed(c->g, c->links, grad_rho, lam, c->stream));
+}
+
+lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (!src || !dst || src == dst || bytes == 0 || bytes % 16 != 0) return LBM_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0) return LBM_EINVAL;
+  return from_hip(launch_stream_copy(src, dst, bytes, static_cast<hipStream_t>(stream)));
 }
 
 lbm_status lbm_destroy(lbm_ctx* c) {

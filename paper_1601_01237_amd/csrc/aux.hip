@@ -261,6 +261,14 @@ __global__ void adjoint_seed_kernel(const Grid g, const uint32_t* __restrict__ l
   }
 }
 
+// Plain streaming copy, 16 bytes per lane per iteration: the reference for
+// how much read + write bandwidth the memory system delivers.
+__global__ void stream_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n16) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n16; i += stride)
+    dst[i] = src[i];
+}
+
 unsigned grid_for(uint64_t n) {
   uint64_t b = (n + TPB - 1) / TPB;
   if (b > 65536ull * 16) b = 65536ull * 16;
@@ -348,6 +356,16 @@ hipError_t launch_adjoint_stream(const Grid& g, const Phys& ph, const uint32_t* 
                                  const float* m, float* lam_out, double* drho0, hipStream_t st) {
   hipLaunchKernelGGL(adjoint_stream_kernel, dim3(grid_for(g.n)), dim3(TPB), 0, st, g, ph, links, lam_in, m,
                      lam_out, drho0);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStream_t st) {
+  const uint64_t n16 = bytes / 16;
+  uint64_t blocks = (n16 + TPB - 1) / TPB;
+  if (blocks > 256ull * 64) blocks = 256ull * 64;  // 64 workgroups per CU, grid-stride beyond that
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(stream_copy_kernel, dim3(static_cast<unsigned>(blocks)), dim3(TPB), 0, st,
+                     static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
   return hipGetLastError();
 }
 

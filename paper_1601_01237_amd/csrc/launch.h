@@ -23,13 +23,15 @@ struct Phys {
 };
 
 struct Tiling {
-  int rows;      // 4 or 8 rows of 64 cells per workgroup
+  int tile;      // workgroup tile shape (index into the shapes of march.hip)
   int zchunk;    // z planes marched per workgroup
   int tiles_x, tiles_y, tiles_z;
   int blocks;
 };
 
-Tiling make_tiling(const Grid& g, int rows, int zchunk);
+// Tile shapes: 0 = 64x8, 1 = 64x12, 2 = 32x16, 3 = 32x24, 4 = 64x4 cells.
+constexpr int TILE_SHAPES = 5;
+Tiling make_tiling(const Grid& g, int tile, int zchunk);
 
 // Diagnostic region (device-side floats).
 struct Region {
@@ -70,6 +72,7 @@ hipError_t launch_adjoint_gather(const Grid& g, const uint32_t* links, float* m,
 hipError_t launch_adjoint_stream(const Grid& g, const Phys& ph, const uint32_t* links,
                                  const float* lam_in, const float* m, float* lam_out,
                                  double* drho0, hipStream_t st);
+hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStream_t st);
 hipError_t launch_adjoint_seed(const Grid& g, const uint32_t* links, const float* grad_rho,
                                float* lam, hipStream_t st);
 

@@ -146,30 +146,6 @@ __device__ __forceinline__ void pair_dots(float vx, float vy, float vz, float cv
   cv[7] = vy + vz; cv[8] = vy - vz;
 }
 
-// Bracket of Eq. (3) at T0 = 1/3: P(v) = 1 + 3 cv + 4.5 cv^2 - 1.5 vv + 4.5 cv^3
-// - 4.5 cv vv, split into the part even in cv and the part odd in cv so that
-// P(+p_k) = ev + od and P(-p_k) = ev - od.
-struct Bracket {
-  float rest;
-  float ev[9];
-  float od[9];
-};
-
-__device__ __forceinline__ void bracket(float vx, float vy, float vz, Bracket& B) {
-  const float vv = vx * vx + vy * vy + vz * vz;
-  const float a = 1.0f - 1.5f * vv;
-  const float b = 3.0f - 4.5f * vv;
-  float cv[9];
-  pair_dots(vx, vy, vz, cv);
-  B.rest = a;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const float t = cv[k] * cv[k];
-    B.ev[k] = a + 4.5f * t;
-    B.od[k] = cv[k] * (b + 4.5f * t);
-  }
-}
-
 __device__ __forceinline__ constexpr float pair_w(int k) { return k < 3 ? WF : WE; }
 
 // Everything a cell needs from its neighbourhood and its populations.
@@ -181,74 +157,117 @@ struct Local {
   float g[2][3]; // g^a = sum_b G^{ab} S^b (force per unit mass, Sec. 2)
 };
 
-// u from the populations; S from the LDS density ring.
-__device__ __forceinline__ void make_local(const float f[2][Q], const float rho_a, const float rho_b,
-                                           const float2 (*pm)[BX + 2], const float2 (*p0)[BX + 2],
-                                           const float2 (*pp)[BX + 2], int ly, int lx,
-                                           const Phys& ph, Local& L) {
-  L.rho[0] = rho_a;
-  L.rho[1] = rho_b;
-  L.rinv = 1.0f / (rho_a + rho_b);
+// Mixture velocity of Eq. (6) from the pulled populations: u = j / rho.
+__device__ __forceinline__ void mixture_velocity(const float f[2][Q], float rho, float u[3]) {
   float d[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) d[k] = (f[0][2 * k + 1] + f[1][2 * k + 1]) - (f[0][2 * k + 2] + f[1][2 * k + 2]);
-  const float jx = d[0] + d[3] + d[4] + d[5] + d[6];
-  const float jy = d[1] + d[3] - d[4] + d[7] + d[8];
-  const float jz = d[2] + d[5] - d[6] + d[7] - d[8];
-  L.u[0] = jx * L.rinv;
-  L.u[1] = jy * L.rinv;
-  L.u[2] = jz * L.rinv;
+  const float rinv = 1.0f / rho;
+  u[0] = (d[0] + d[3] + d[4] + d[5] + d[6]) * rinv;
+  u[1] = (d[1] + d[3] - d[4] + d[7] + d[8]) * rinv;
+  u[2] = (d[2] + d[5] - d[6] + d[7] - d[8]) * rinv;
+}
 
-  // Neighbour densities rho~(x + p_k) - rho~(x - p_k) for each pair.
-  // Ring rows are indexed [y + 1][x + 1] relative to the tile.
-  float2 e[9];
-  auto R = [&](const float2 (*pl)[BX + 2], int dy, int dx) { return pl[ly + dy][lx + dx]; };
-  auto dif = [](float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); };
-  e[0] = dif(R(p0, 0, 1), R(p0, 0, -1));
-  e[1] = dif(R(p0, 1, 0), R(p0, -1, 0));
-  e[2] = dif(R(pp, 0, 0), R(pm, 0, 0));
-  e[3] = dif(R(p0, 1, 1), R(p0, -1, -1));
-  e[4] = dif(R(p0, -1, 1), R(p0, 1, -1));
-  e[5] = dif(R(pp, 0, 1), R(pm, 0, -1));
-  e[6] = dif(R(pm, 0, 1), R(pp, 0, -1));
-  e[7] = dif(R(pp, 1, 0), R(pm, -1, 0));
-  e[8] = dif(R(pm, 1, 0), R(pp, -1, 0));
-  const float2 sx = make_float2(WF * e[0].x + WE * (e[3].x + e[4].x + e[5].x + e[6].x),
-                                WF * e[0].y + WE * (e[3].y + e[4].y + e[5].y + e[6].y));
-  const float2 sy = make_float2(WF * e[1].x + WE * (e[3].x - e[4].x + e[7].x + e[8].x),
-                                WF * e[1].y + WE * (e[3].y - e[4].y + e[7].y + e[8].y));
-  const float2 sz = make_float2(WF * e[2].x + WE * (e[5].x - e[6].x + e[7].x - e[8].x),
-                                WF * e[2].y + WE * (e[5].y - e[6].y + e[7].y - e[8].y));
-  L.S[0][0] = sx.x; L.S[0][1] = sy.x; L.S[0][2] = sz.x;
-  L.S[1][0] = sx.y; L.S[1][1] = sy.y; L.S[1][2] = sz.y;
+// Shan-Chen neighbour sum S^b(x) = sum_i w_i c_i rho~^b(x + c_i) (Eq. 7) from
+// the LDS density ring, in two parts.  `at` is the cell's position in a ring
+// plane (row stride EX).  shan_chen_partial takes the 13 neighbours in planes
+// z-1 (pm) and z (p0); shan_chen_finish adds the 5 in plane z+1 (pp).  Both
+// species at once (float2 = rho~^A, rho~^B).
+template <int EX>
+__device__ __forceinline__ void shan_chen_partial(const float2* pm, const float2* p0, int at, float2 S[3]) {
+  auto R = [&](const float2* pl, int dy, int dx) { return pl[at + dy * EX + dx]; };
+  const float2 a = R(p0, 0, 1), b = R(p0, 0, -1), c = R(p0, 1, 0), d = R(p0, -1, 0);
+  const float2 e = R(p0, 1, 1), f = R(p0, -1, 1), g = R(p0, 1, -1), h = R(p0, -1, -1);
+  const float2 m0 = R(pm, 0, 0), mx = R(pm, 0, 1), mxm = R(pm, 0, -1), my = R(pm, 1, 0), mym = R(pm, -1, 0);
+  // in plane: faces (w = 1/18) and xy edges (w = 1/36); plane below: c_z = -1
+  S[0].x = fmaf(WF, a.x - b.x, WE * (((e.x + f.x) - (g.x + h.x)) + (mx.x - mxm.x)));
+  S[0].y = fmaf(WF, a.y - b.y, WE * (((e.y + f.y) - (g.y + h.y)) + (mx.y - mxm.y)));
+  S[1].x = fmaf(WF, c.x - d.x, WE * (((e.x + g.x) - (f.x + h.x)) + (my.x - mym.x)));
+  S[1].y = fmaf(WF, c.y - d.y, WE * (((e.y + g.y) - (f.y + h.y)) + (my.y - mym.y)));
+  S[2].x = -fmaf(WF, m0.x, WE * ((mx.x + mxm.x) + (my.x + mym.x)));
+  S[2].y = -fmaf(WF, m0.y, WE * ((mx.y + mxm.y) + (my.y + mym.y)));
+}
+
+template <int EX>
+__device__ __forceinline__ void shan_chen_finish(const float2* pp, int at, float2 S[3]) {
+  auto R = [&](int dy, int dx) { return pp[at + dy * EX + dx]; };
+  const float2 p0 = R(0, 0), px = R(0, 1), pxm = R(0, -1), py = R(1, 0), pym = R(-1, 0);
+  S[0].x = fmaf(WE, px.x - pxm.x, S[0].x);
+  S[0].y = fmaf(WE, px.y - pxm.y, S[0].y);
+  S[1].x = fmaf(WE, py.x - pym.x, S[1].x);
+  S[1].y = fmaf(WE, py.y - pym.y, S[1].y);
+  S[2].x += fmaf(WF, p0.x, WE * ((px.x + pxm.x) + (py.x + pym.x)));
+  S[2].y += fmaf(WF, p0.y, WE * ((px.y + pxm.y) + (py.y + pym.y)));
+}
+
+__device__ __forceinline__ void make_local(const float rho_a, const float rho_b, const float u[3],
+                                           const float2 S[3], const Phys& ph, Local& L) {
+  L.rho[0] = rho_a;
+  L.rho[1] = rho_b;
+  L.rinv = 1.0f / (rho_a + rho_b);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    L.g[0][k] = ph.g_ab * L.S[1][k];
-    L.g[1][k] = ph.g_ba * L.S[0][k];
+    L.u[k] = u[k];
+    L.S[0][k] = S[k].x;
+    L.S[1][k] = S[k].y;
+    L.g[0][k] = ph.g_ab * S[k].y;  // g^A = G^{AB} S^B
+    L.g[1][k] = ph.g_ba * S[k].x;  // g^B = G^{BA} S^A
   }
 }
 
 // BGK collision (Eq. 2) plus the exact-difference forcing term, in place:
-//   f*_i = (1 - w) f_i + w_i rho^a [(w - 1) P_i(u) + P_i(u + g^a)],  w = 1/tau_a.
+//   f*_i = (1 - w) f_i + w_i rho^a [(w - 1) P_i(u) + P_i(u + g^a)],  w = 1/tau_a,
+// with P the bracket of Eq. (3) at T0 = 1/3,
+//   P(v) = 1 + 3 cv + 4.5 cv^2 - 1.5 vv + 4.5 cv^3 - 4.5 cv vv,
+// evaluated per opposite pair as P(+-p_k) = even +- odd in cv.
+__device__ __forceinline__ float pair_dot(int k, float vx, float vy, float vz) {
+  switch (k) {
+    case 0: return vx;
+    case 1: return vy;
+    case 2: return vz;
+    case 3: return vx + vy;
+    case 4: return vx - vy;
+    case 5: return vx + vz;
+    case 6: return vx - vz;
+    case 7: return vy + vz;
+    default: return vy - vz;
+  }
+}
+
 __device__ __forceinline__ void collide(float f[2][Q], const Local& L, const Phys& ph) {
-  Bracket Bu;
-  bracket(L.u[0], L.u[1], L.u[2], Bu);
+  const float ux = L.u[0], uy = L.u[1], uz = L.u[2];
+  const float uu = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+  const float au = fmaf(-1.5f, uu, 1.0f);
+  const float bu = fmaf(-4.5f, uu, 3.0f);
+  float vx[2], vy[2], vz[2], av[2], bv[2], om1[2], keep[2], r[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    Bracket Bv;
-    bracket(L.u[0] + L.g[s][0], L.u[1] + L.g[s][1], L.u[2] + L.g[s][2], Bv);
-    const float om = ph.omega[s];
-    const float om1 = om - 1.0f;
-    const float keep = 1.0f - om;
-    const float r = L.rho[s];
-    f[s][0] = keep * f[s][0] + (W0 * r) * (om1 * Bu.rest + Bv.rest);
+    vx[s] = ux + L.g[s][0];
+    vy[s] = uy + L.g[s][1];
+    vz[s] = uz + L.g[s][2];
+    const float vv = fmaf(vx[s], vx[s], fmaf(vy[s], vy[s], vz[s] * vz[s]));
+    av[s] = fmaf(-1.5f, vv, 1.0f);
+    bv[s] = fmaf(-4.5f, vv, 3.0f);
+    om1[s] = ph.omega[s] - 1.0f;
+    keep[s] = 1.0f - ph.omega[s];
+    r[s] = L.rho[s];
+    f[s][0] = fmaf(keep[s], f[s][0], (W0 * r[s]) * fmaf(om1[s], au, av[s]));
+  }
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const float ke = om1 * Bu.ev[k] + Bv.ev[k];
-      const float ko = om1 * Bu.od[k] + Bv.od[k];
-      const float wr = pair_w(k) * r;
-      f[s][2 * k + 1] = keep * f[s][2 * k + 1] + wr * (ke + ko);
-      f[s][2 * k + 2] = keep * f[s][2 * k + 2] + wr * (ke - ko);
+  for (int k = 0; k < 9; ++k) {
+    const float cu = pair_dot(k, ux, uy, uz);
+    const float tu = cu * cu;
+    const float eu = fmaf(4.5f, tu, au);
+    const float ou = cu * fmaf(4.5f, tu, bu);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const float cv = pair_dot(k, vx[s], vy[s], vz[s]);
+      const float tv = cv * cv;
+      const float ke = fmaf(om1[s], eu, fmaf(4.5f, tv, av[s]));
+      const float ko = fmaf(om1[s], ou, cv * fmaf(4.5f, tv, bv[s]));
+      const float wr = pair_w(k) * r[s];
+      f[s][2 * k + 1] = fmaf(keep[s], f[s][2 * k + 1], wr * (ke + ko));
+      f[s][2 * k + 2] = fmaf(keep[s], f[s][2 * k + 2], wr * (ke - ko));
     }
   }
 }
@@ -385,48 +404,64 @@ __device__ __forceinline__ float min_image(float d, float n) { return d - n * ri
 // ---------------------------------------------------------------------------
 // The march
 // ---------------------------------------------------------------------------
-template <Storage S, bool WALLS, Mode M, int ROWS>
-__global__ void __launch_bounds__(BX * ROWS)
+
+// Workgroup shape: BXT x ROWS "own" lanes (one cell column each, a multiple of
+// 64) followed by HW "halo" waves that compute the densities of the one-cell
+// ring around the tile.  Own waves keep the pulled populations of planes z
+// and z+1 in registers; halo waves run one plane ahead of them, so their
+// loads overlap the own waves' collision.  The density ring has 5 slots:
+// plane p_k (the k-th plane a workgroup loads) lives in slot k % 5.  There is
+// one barrier per plane (k >= 1): before barrier k the own waves have written
+// their cells of p_k and the halo waves the ring of p_0 .. p_{k+1}; after it
+// the own waves finish plane p_{k-1} (needs p_{k-2} .. p_k) and start the
+// Shan-Chen sum of p_k from p_{k-1} and p_k, while the halo waves fill p_{k+2}
+// into slot (k+2) % 5, whose last reader finished before barrier k-1.
+template <int BXT, int ROWS, int HW>
+struct Shape {
+  static constexpr int NOWN = BXT * ROWS;
+  static constexpr int EX = BXT + 2;
+  static constexpr int EY = ROWS + 2;
+  static constexpr int NH = 2 * EX + 2 * ROWS;
+  static constexpr int NT = NOWN + 64 * HW;
+  static constexpr int SLOTS = 5;
+  static_assert(NOWN % 64 == 0, "own lanes fill whole waves");
+  static_assert(NH <= 64 * HW, "one halo cell per halo lane");
+};
+
+// Ring position of halo cell h: bottom row, top row, left column, right column.
+template <int BXT, int ROWS>
+__device__ __forceinline__ void halo_pos(int h, int& hx, int& hy) {
+  constexpr int EX = BXT + 2;
+  if (h < EX) { hx = h - 1; hy = -1; }
+  else if (h < 2 * EX) { hx = h - EX - 1; hy = ROWS; }
+  else if (h < 2 * EX + ROWS) { hx = -1; hy = h - 2 * EX; }
+  else { hx = BXT; hy = h - 2 * EX - ROWS; }
+}
+
+template <Storage S, bool WALLS, Mode M, int BXT, int ROWS, int HW>
+__global__ void __launch_bounds__(BXT * ROWS + 64 * HW)
 march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
+  using Sh = Shape<BXT, ROWS, HW>;
   using Tr = StorageTraits<S>;
   using T = typename Tr::T;
-  constexpr int NT = BX * ROWS;
-  constexpr int EX = BX + 2;
-  constexpr int NH = 2 * EX + 2 * ROWS;  // halo cells around the tile
-  static_assert(NH <= NT, "one halo cell per thread at most");
-  __shared__ float2 ring[4][ROWS + 2][EX];
-  __shared__ double red[(NT / 64) * 16];
+  constexpr int EX = Sh::EX;
+  constexpr int PLANE = Sh::EX * Sh::EY;
+  __shared__ float2 ring[Sh::SLOTS * PLANE];
+  __shared__ double red[(Sh::NT / 64) * 16];
 
   const int tid = threadIdx.x;
-  const int tx = tid % BX, ty = tid / BX;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int tiles_xy = tl.tiles_x * tl.tiles_y;
   const int bz = b / tiles_xy;
   const int rem = b - bz * tiles_xy;
   const int byy = rem / tl.tiles_x;
   const int bxx = rem - byy * tl.tiles_x;
-  const int x0 = bxx * BX, y0 = byy * ROWS, z0 = bz * tl.zchunk;
+  const int x0 = bxx * BXT, y0 = byy * ROWS, z0 = bz * tl.zchunk;
   const int z1 = min(z0 + tl.zchunk, g.nz);
+  const int kmax = z1 - z0 + 1;  // planes p_k = z0 - 1 + k for k = 0..kmax
 
   const uint64_t n = g.n;
   const uint32_t ppb = g.nxy * static_cast<uint32_t>(sizeof(T));  // bytes of one population plane
-
-  // This thread's own column (always computed; only owners update cells).
-  const int ex = x0 + tx, ey = y0 + ty;
-  const bool owner = ex < g.nx && ey < g.ny;
-  const Column col = make_column<T>(ex, ey, g);
-  const uint32_t col_b = col.y[1] + col.x[1];             // byte offset in a plane
-  const uint32_t col_off = col_b / static_cast<uint32_t>(sizeof(T));  // element offset
-
-  // Halo column of this thread, if any: bottom row, top row, left, right.
-  const bool has_halo = tid < NH;
-  int hx = 0, hy = 0;
-  if (tid < EX) { hx = tid - 1; hy = -1; }
-  else if (tid < 2 * EX) { hx = tid - EX - 1; hy = ROWS; }
-  else if (tid < 2 * EX + ROWS) { hx = -1; hy = tid - 2 * EX; }
-  else { hx = BX; hy = tid - 2 * EX - ROWS; }
-  const Column hcol = make_column<T>(x0 + hx, y0 + hy, g);
-  const uint32_t hcol_off = (hcol.y[1] + hcol.x[1]) / static_cast<uint32_t>(sizeof(T));
 
   float ws[2][3];
 #pragma unroll
@@ -436,153 +471,200 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
     ws[s][2] = WE * ph.shift[s];
   }
 
-  float cur[2][Q], nxt[2][Q];
-  float cur_rho[2] = {0.f, 0.f}, nxt_rho[2] = {0.f, 0.f};
-  uint32_t cur_links = 0, nxt_links = 0;
-
-  // Per-thread diagnostic / gradient accumulators.
   constexpr int NV = (M == Mode::Moments) ? 16 : 3;
   double acc[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) acc[k] = 0.0;
 
-  for (int p = z0 - 1; p <= z1; ++p) {
-    const int zw = wrap(p, g.nz);
-    __amdgpu_buffer_rsrc_t rz[3];
-    rz[0] = plane_rsrc<T>(io.src, wrap(p - 1, g.nz), g);
-    rz[1] = plane_rsrc<T>(io.src, zw, g);
-    rz[2] = plane_rsrc<T>(io.src, wrap(p + 1, g.nz), g);
-    const uint32_t zo1 = static_cast<uint32_t>(zw) * g.nxy;  // element offset of plane p in a cell field
-    const int slot = (p + 4) & 3;
+  if (tid < Sh::NOWN) {
+    // ------------------------------------------------------------ own waves
+    const int tx = tid % BXT, ty = tid / BXT;
+    const int ex = x0 + tx, ey = y0 + ty;
+    const bool owner = ex < g.nx && ey < g.ny;  // ragged edge lanes only feed the ring
+    const Column col = make_column<T>(ex, ey, g);
+    const uint32_t col_b = col.y[1] + col.x[1];
+    const uint32_t col_off = col_b / static_cast<uint32_t>(sizeof(T));
+    const int at = (ty + 1) * EX + tx + 1;
 
-    // ---- phase A: pull plane p, reduce densities into the ring ----------
-    {
-      if constexpr (WALLS) nxt_links = io.links[zo1 + col_off];
+    float cur[2][Q], nxt[2][Q];
+    float cur_rho[2] = {0.f, 0.f}, nxt_rho[2] = {0.f, 0.f};
+    float cur_u[3] = {0.f, 0.f, 0.f}, nxt_u[3] = {0.f, 0.f, 0.f};
+    float2 cur_S[3], nxt_S[3];  // Shan-Chen sums from planes z-1 and z
+#pragma unroll
+    for (int c = 0; c < 3; ++c) cur_S[c] = nxt_S[c] = make_float2(0.f, 0.f);
+    uint32_t cur_links = 0, nxt_links = 0;
+    int slot = 0;  // k % 5
+
+    for (int k = 0; k <= kmax; ++k) {
+      const int p = z0 - 1 + k;
+      const int zw = wrap(p, g.nz);
+      __amdgpu_buffer_rsrc_t rz[3];
+      rz[0] = plane_rsrc<T>(io.src, wrap(p - 1, g.nz), g);
+      rz[1] = plane_rsrc<T>(io.src, zw, g);
+      rz[2] = plane_rsrc<T>(io.src, wrap(p + 1, g.nz), g);
+      if constexpr (WALLS) nxt_links = io.links[static_cast<uint32_t>(zw) * g.nxy + col_off];
       const bool solid = WALLS && (nxt_links & 1u);
       if (!solid) {
         pull<S, WALLS>(rz, ppb, col, nxt_links, ws, nxt);
         nxt_rho[0] = sum19(nxt[0]);
         nxt_rho[1] = sum19(nxt[1]);
-        ring[slot][ty + 1][tx + 1] = make_float2(nxt_rho[0], nxt_rho[1]);
+        ring[slot * PLANE + at] = make_float2(nxt_rho[0], nxt_rho[1]);
+        mixture_velocity(nxt, nxt_rho[0] + nxt_rho[1], nxt_u);
       } else {
-        ring[slot][ty + 1][tx + 1] = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
+        ring[slot * PLANE + at] = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
       }
+
+      if (k >= 1) {
+        __syncthreads();
+        const int sm1 = slot >= 1 ? slot - 1 : slot + 4;  // (k-1) % 5
+        if (k >= 2) {
+          const int z = p - 1;
+          const int zc = wrap(z, g.nz);
+          const bool csolid = WALLS && (cur_links & 1u);
+          const uint32_t cell = static_cast<uint32_t>(zc) * g.nxy + col_off;
+          if (owner) {
+            if constexpr (M == Mode::Step) {
+              if (!csolid) {
+                shan_chen_finish<EX>(ring + slot * PLANE, at, cur_S);
+                Local L;
+                make_local(cur_rho[0], cur_rho[1], cur_u, cur_S, ph, L);
+                collide(cur, L, ph);
+                const __amdgpu_buffer_rsrc_t rd = plane_rsrc<T>(io.dst, zc, g);
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+#pragma unroll
+                  for (int i = 0; i < Q; ++i) {
+                    float v = cur[s][i];
+                    if constexpr (Tr::shifted) v -= ws[s][i == 0 ? 0 : (i <= 6 ? 1 : 2)];
+                    buf_store<T>(Tr::encode(v), rd, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
+                  }
+                }
+              }
+            } else if constexpr (M == Mode::Moments) {
+              float ra = 0.f, rb = 0.f, uf[3] = {0.f, 0.f, 0.f};
+              if (!csolid) {
+                shan_chen_finish<EX>(ring + slot * PLANE, at, cur_S);
+                Local L;
+                make_local(cur_rho[0], cur_rho[1], cur_u, cur_S, ph, L);
+                ra = L.rho[0];
+                rb = L.rho[1];
+                // u_F = u + g/2, g = sum_a rho^a g^a / rho  (Eqs. 8-9)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                  uf[c] = L.u[c] + 0.5f * (ra * L.g[0][c] + rb * L.g[1][c]) * L.rinv;
+                const double rho = static_cast<double>(ra) + static_cast<double>(rb);
+                acc[0] += ra;
+                acc[1] += rb;
+                acc[2] += rho * uf[0];
+                acc[3] += rho * uf[1];
+                acc[4] += rho * uf[2];
+                const double sp = sqrt(static_cast<double>(uf[0]) * uf[0] + static_cast<double>(uf[1]) * uf[1] +
+                                       static_cast<double>(uf[2]) * uf[2]);
+                const bool finite = isfinite(ra) && isfinite(rb) && isfinite(uf[0]) && isfinite(uf[1]) &&
+                                    isfinite(uf[2]);
+                acc[5] = fmax(acc[5], finite ? sp : 0.0);
+                acc[6] += finite ? 0.0 : 1.0;
+                acc[7] += 1.0;
+                const Region& R = io.region;
+                const float dx = min_image(static_cast<float>(col_off % g.nx) - R.cx, static_cast<float>(g.nx));
+                const float dy = min_image(static_cast<float>(col_off / g.nx) - R.cy, static_cast<float>(g.ny));
+                const float dz = min_image(static_cast<float>(zc) - R.cz, static_cast<float>(g.nz));
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const double pr = (1.0 / 3.0) * rho - static_cast<double>(R.p_g) * (1.0 / 3.0) *
+                                                          static_cast<double>(ra) * static_cast<double>(rb);
+                if (r2 < R.r_in2) { acc[8] += pr; acc[9] += 1.0; }
+                if (r2 > R.r_out2) { acc[10] += pr; acc[11] += 1.0; }
+                if (ra > R.thr) { acc[12] += 1.0; acc[13] += dx; acc[14] += dy; acc[15] += dz; }
+              }
+              if (io.rho_out) {
+                io.rho_out[cell] = ra;
+                io.rho_out[n + cell] = rb;
+              }
+              if (io.uf_out) {
+                io.uf_out[cell] = uf[0];
+                io.uf_out[n + cell] = uf[1];
+                io.uf_out[2 * n + cell] = uf[2];
+              }
+            } else {  // Mode::Adjoint
+              float mo[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+              float sb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+              if (!csolid) {
+                shan_chen_finish<EX>(ring + slot * PLANE, at, cur_S);
+                Local L;
+                make_local(cur_rho[0], cur_rho[1], cur_u, cur_S, ph, L);
+                float lam[2][Q];
+                const __amdgpu_buffer_rsrc_t rl = plane_rsrc<float>(io.lam, zc, g);
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                  for (int i = 0; i < Q; ++i)
+                    lam[s][i] = buf_load<float>(rl, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
+                adjoint_cell(cur, lam, L, ph, mo, sb, acc);
+              }
+#pragma unroll
+              for (int c = 0; c < 5; ++c) io.m[c * n + cell] = mo[c];
+#pragma unroll
+              for (int c = 0; c < 6; ++c) io.sbar[c * n + cell] = sb[c];
+            }
+          }
+        }
+        // Planes p_{k-1} and p_k are complete: the first part of S for plane p_k.
+        if (k < kmax) shan_chen_partial<EX>(ring + sm1 * PLANE, ring + slot * PLANE, at, nxt_S);
+      }
+
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) cur[s][i] = nxt[s][i];
+        cur_rho[s] = nxt_rho[s];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cur_u[c] = nxt_u[c];
+        cur_S[c] = nxt_S[c];
+      }
+      cur_links = nxt_links;
+      slot = slot == 4 ? 0 : slot + 1;
     }
-    if (has_halo) {
+  } else {
+    // ----------------------------------------------------------- halo waves
+    const int h = tid - Sh::NOWN;
+    const bool has = h < Sh::NH;
+    int hx = 0, hy = 0;
+    halo_pos<BXT, ROWS>(has ? h : 0, hx, hy);
+    const Column hcol = make_column<T>(x0 + hx, y0 + hy, g);
+    const uint32_t hcol_off = (hcol.y[1] + hcol.x[1]) / static_cast<uint32_t>(sizeof(T));
+    const int hat = (hy + 1) * EX + hx + 1;
+
+    auto halo_plane = [&](int k) {
+      const int p = z0 - 1 + k;
+      const int zw = wrap(p, g.nz);
       uint32_t hl = 0;
-      if constexpr (WALLS) hl = io.links[zo1 + hcol_off];
+      if constexpr (WALLS) hl = io.links[static_cast<uint32_t>(zw) * g.nxy + hcol_off];
       float2 r;
       if (WALLS && (hl & 1u)) {
         r = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
       } else {
+        __amdgpu_buffer_rsrc_t rz[3];
+        rz[0] = plane_rsrc<T>(io.src, wrap(p - 1, g.nz), g);
+        rz[1] = plane_rsrc<T>(io.src, zw, g);
+        rz[2] = plane_rsrc<T>(io.src, wrap(p + 1, g.nz), g);
         float hf[2][Q];
         pull<S, WALLS>(rz, ppb, hcol, hl, ws, hf);
         r = make_float2(sum19(hf[0]), sum19(hf[1]));
       }
-      ring[slot][hy + 1][hx + 1] = r;
-    }
+      ring[(k % 5) * PLANE + hat] = r;
+    };
 
-    // ---- phase B: update plane p - 1 --------------------------------------
-    if (p >= z0 + 1) {
+    // Planes p_0 .. p_2 before the first barrier (k = 1), then p_{k+2}
+    // right after barrier k: one plane ahead of the own waves.
+    if (has) {
+      for (int k = 0; k <= min(2, kmax); ++k) halo_plane(k);
+    }
+    for (int k = 1; k <= kmax; ++k) {
       __syncthreads();
-      const int z = p - 1;
-      const bool solid = WALLS && (cur_links & 1u);
-      const uint32_t cell = static_cast<uint32_t>(wrap(z, g.nz)) * g.nxy + col_off;
-      if (owner) {
-        const float2 (*pm)[EX] = ring[(z - 1 + 4) & 3];
-        const float2 (*p0)[EX] = ring[(z + 4) & 3];
-        const float2 (*pp)[EX] = ring[(z + 1 + 4) & 3];
-        if constexpr (M == Mode::Step) {
-          if (!solid) {
-            Local L;
-            make_local(cur, cur_rho[0], cur_rho[1], pm, p0, pp, ty + 1, tx + 1, ph, L);
-            collide(cur, L, ph);
-            const __amdgpu_buffer_rsrc_t rd = plane_rsrc<T>(io.dst, wrap(z, g.nz), g);
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-#pragma unroll
-              for (int i = 0; i < Q; ++i) {
-                float v = cur[s][i];
-                if constexpr (Tr::shifted) v -= ws[s][i == 0 ? 0 : (i <= 6 ? 1 : 2)];
-                buf_store<T>(Tr::encode(v), rd, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
-              }
-            }
-          }
-        } else if constexpr (M == Mode::Moments) {
-          float ra = 0.f, rb = 0.f, uf[3] = {0.f, 0.f, 0.f};
-          if (!solid) {
-            Local L;
-            make_local(cur, cur_rho[0], cur_rho[1], pm, p0, pp, ty + 1, tx + 1, ph, L);
-            ra = L.rho[0];
-            rb = L.rho[1];
-            // u_F = u + g/2, g = sum_a rho^a g^a / rho  (Eqs. 8-9)
-#pragma unroll
-            for (int k = 0; k < 3; ++k)
-              uf[k] = L.u[k] + 0.5f * (ra * L.g[0][k] + rb * L.g[1][k]) * L.rinv;
-            const double rho = static_cast<double>(ra) + static_cast<double>(rb);
-            acc[0] += ra;
-            acc[1] += rb;
-            acc[2] += rho * uf[0];
-            acc[3] += rho * uf[1];
-            acc[4] += rho * uf[2];
-            const double sp = sqrt(static_cast<double>(uf[0]) * uf[0] +
-                                   static_cast<double>(uf[1]) * uf[1] +
-                                   static_cast<double>(uf[2]) * uf[2]);
-            const bool finite = isfinite(ra) && isfinite(rb) && isfinite(uf[0]) &&
-                                isfinite(uf[1]) && isfinite(uf[2]);
-            acc[5] = fmax(acc[5], finite ? sp : 0.0);
-            acc[6] += finite ? 0.0 : 1.0;
-            acc[7] += 1.0;
-            const Region& R = io.region;
-            const float dx = min_image(static_cast<float>(col_off % g.nx) - R.cx, static_cast<float>(g.nx));
-            const float dy = min_image(static_cast<float>(col_off / g.nx) - R.cy, static_cast<float>(g.ny));
-            const float dz = min_image(static_cast<float>(wrap(z, g.nz)) - R.cz, static_cast<float>(g.nz));
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const double pr = (1.0 / 3.0) * rho - static_cast<double>(R.p_g) * (1.0 / 3.0) *
-                                                      static_cast<double>(ra) * static_cast<double>(rb);
-            if (r2 < R.r_in2) { acc[8] += pr; acc[9] += 1.0; }
-            if (r2 > R.r_out2) { acc[10] += pr; acc[11] += 1.0; }
-            if (ra > R.thr) { acc[12] += 1.0; acc[13] += dx; acc[14] += dy; acc[15] += dz; }
-          }
-          if (io.rho_out) {
-            io.rho_out[cell] = ra;
-            io.rho_out[n + cell] = rb;
-          }
-          if (io.uf_out) {
-            io.uf_out[cell] = uf[0];
-            io.uf_out[n + cell] = uf[1];
-            io.uf_out[2 * n + cell] = uf[2];
-          }
-        } else {  // Mode::Adjoint
-          float mo[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-          float sb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-          if (!solid) {
-            Local L;
-            make_local(cur, cur_rho[0], cur_rho[1], pm, p0, pp, ty + 1, tx + 1, ph, L);
-            float lam[2][Q];
-            const __amdgpu_buffer_rsrc_t rl = plane_rsrc<float>(io.lam, wrap(z, g.nz), g);
-#pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-              for (int i = 0; i < Q; ++i) lam[s][i] = buf_load<float>(rl, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
-            adjoint_cell(cur, lam, L, ph, mo, sb, acc);
-          }
-#pragma unroll
-          for (int k = 0; k < 5; ++k) io.m[k * n + cell] = mo[k];
-#pragma unroll
-          for (int k = 0; k < 6; ++k) io.sbar[k * n + cell] = sb[k];
-        }
-      }
+      if (has && k + 2 <= kmax) halo_plane(k + 2);
     }
-
-    // ---- rotate registers ---------------------------------------------------
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-#pragma unroll
-      for (int i = 0; i < Q; ++i) cur[s][i] = nxt[s][i];
-      cur_rho[s] = nxt_rho[s];
-    }
-    cur_links = nxt_links;
   }
 
   if constexpr (M != Mode::Step) {
@@ -597,16 +679,32 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
 // ---------------------------------------------------------------------------
 // Launch
 // ---------------------------------------------------------------------------
-Tiling make_tiling(const Grid& g, int rows, int zchunk) {
+
+// Tile shapes selectable at run time: (columns, rows, halo waves).
+struct TileShape {
+  int bx, rows, hw;
+};
+constexpr TileShape TILES[] = {{64, 8, 3}, {64, 12, 3}, {32, 16, 2}, {32, 24, 2}, {64, 4, 3}};
+constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
+
+Tiling make_tiling(const Grid& g, int tile, int zchunk) {
   Tiling t{};
-  t.rows = rows;
-  t.tiles_x = (g.nx + BX - 1) / BX;
-  t.tiles_y = (g.ny + rows - 1) / rows;
+  if (tile < 0 || tile >= NTILES) {
+    t.blocks = -1;
+    return t;
+  }
+  t.tile = tile;
+  const TileShape sh = TILES[tile];
+  t.tiles_x = (g.nx + sh.bx - 1) / sh.bx;
+  t.tiles_y = (g.ny + sh.rows - 1) / sh.rows;
   const long long txy = static_cast<long long>(t.tiles_x) * t.tiles_y;
   if (zchunk <= 0) {
-    // Aim for about 2048 workgroups (8 per CU) with the longest march.
-    long long zc = (static_cast<long long>(g.nz) * txy + 2047) / 2048;
-    if (zc < 4) zc = 4;
+    // One workgroup fills a CU (11 waves); march 16 to 32 planes so that the
+    // two planes each workgroup re-reads at its ends cost at most 1/8, with
+    // about one workgroup per CU (256 CUs) per round.
+    long long zc = (static_cast<long long>(g.nz) * txy + 255) / 256;
+    if (zc < 16) zc = 16;
+    if (zc > 32) zc = 32;
     if (zc > g.nz) zc = g.nz;
     zchunk = static_cast<int>(zc);
   }
@@ -618,21 +716,38 @@ Tiling make_tiling(const Grid& g, int rows, int zchunk) {
   return t;
 }
 
-template <Storage S, bool WALLS, Mode M>
-static hipError_t launch_rows(const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io,
-                              hipStream_t st) {
-  if (t.rows == 4) {
-    hipLaunchKernelGGL((march_kernel<S, WALLS, M, 4>), dim3(t.blocks), dim3(BX * 4), 0, st, g, ph, t, io);
-  } else {
-    hipLaunchKernelGGL((march_kernel<S, WALLS, M, 8>), dim3(t.blocks), dim3(BX * 8), 0, st, g, ph, t, io);
-  }
+template <Storage S, bool WALLS, Mode M, int BXT, int ROWS, int HW>
+static hipError_t launch_shape(const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io,
+                               hipStream_t st) {
+  using Sh = Shape<BXT, ROWS, HW>;
+  hipLaunchKernelGGL((march_kernel<S, WALLS, M, BXT, ROWS, HW>), dim3(t.blocks), dim3(Sh::NT), 0, st, g, ph, t,
+                     io);
   return hipGetLastError();
+}
+
+template <Storage S, bool WALLS, Mode M>
+static hipError_t launch_tile(const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io,
+                              hipStream_t st) {
+  if constexpr (M == Mode::Step) {
+    switch (t.tile) {
+      case 0: return launch_shape<S, WALLS, M, 64, 8, 3>(g, ph, t, io, st);
+      case 1: return launch_shape<S, WALLS, M, 64, 12, 3>(g, ph, t, io, st);
+      case 2: return launch_shape<S, WALLS, M, 32, 16, 2>(g, ph, t, io, st);
+      case 3: return launch_shape<S, WALLS, M, 32, 24, 2>(g, ph, t, io, st);
+      case 4: return launch_shape<S, WALLS, M, 64, 4, 3>(g, ph, t, io, st);
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    // Diagnostics and the adjoint use one shape (tile 0).
+    if (t.tile != 0) return hipErrorInvalidValue;
+    return launch_shape<S, WALLS, M, 64, 8, 3>(g, ph, t, io, st);
+  }
 }
 
 template <Storage S, Mode M>
 static hipError_t launch_walls(const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io,
                                hipStream_t st) {
-  return io.links ? launch_rows<S, true, M>(g, ph, t, io, st) : launch_rows<S, false, M>(g, ph, t, io, st);
+  return io.links ? launch_tile<S, true, M>(g, ph, t, io, st) : launch_tile<S, false, M>(g, ph, t, io, st);
 }
 
 template <Storage S>
@@ -647,7 +762,7 @@ static hipError_t launch_mode(Mode mode, const Grid& g, const Phys& ph, const Ti
 
 hipError_t launch_march(Storage s, Mode mode, const Grid& g, const Phys& ph, const Tiling& t,
                         const MarchIO& io, hipStream_t st) {
-  if (t.blocks <= 0 || (t.rows != 4 && t.rows != 8)) return hipErrorInvalidValue;
+  if (t.blocks <= 0) return hipErrorInvalidValue;
   if (mode == Mode::Adjoint) {
     if (s != Storage::F32) return hipErrorInvalidValue;
     return launch_walls<Storage::F32, Mode::Adjoint>(g, ph, t, io, st);

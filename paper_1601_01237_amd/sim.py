@@ -45,10 +45,11 @@ class Sim:
     rho_shift : per-species shift of the 16-bit forms; default: mean density.
     solid : optional bool array (nz, ny, nx) of wall cells.
     rho_wall : wall potential rho_s^a (Sec. 4).
+    tile, zchunk : tiling of the step kernel (results do not depend on it).
     """
 
     def __init__(self, rho0, tau=(1.0, 1.0), G=-1.0, storage="fp32", rho_shift=None,
-                 solid=None, rho_wall=(0.0, 0.0), device="cuda:0", rows=None, zchunk=None):
+                 solid=None, rho_wall=(0.0, 0.0), device="cuda:0", tile=None, zchunk=None):
         self.lib = _lib.load()
         self.device = torch.device(device)
         rho0 = torch.as_tensor(np.asarray(rho0, dtype=np.float64))
@@ -91,8 +92,8 @@ class Sim:
                 C.byref(ctx), C.byref(p), _ptr(self.bufs[0]), _ptr(self.bufs[1]),
                 _ptr(self.solid_dev), _ptr(self.rho0_dev), C.c_void_p(self.stream.cuda_stream)))
         self.ctx = ctx
-        if rows is not None or zchunk is not None:
-            self.set_tiling(rows or 8, zchunk or 0)
+        if tile is not None or zchunk is not None:
+            self.set_tiling(tile or 0, zchunk or 0)
 
     # -- lifetime --------------------------------------------------------------
     def close(self):
@@ -117,8 +118,9 @@ class Sim:
     def step(self, n=1):
         _lib.check("lbm_step", self.lib.lbm_step(self.ctx, int(n)))
 
-    def set_tiling(self, rows=8, zchunk=0):
-        _lib.check("lbm_set_tiling", self.lib.lbm_set_tiling(self.ctx, int(rows), int(zchunk)))
+    def set_tiling(self, tile=0, zchunk=0):
+        """Tile shape of the step kernel (0..4, see lbm_set_tiling) and z planes per workgroup."""
+        _lib.check("lbm_set_tiling", self.lib.lbm_set_tiling(self.ctx, int(tile), int(zchunk)))
 
     @property
     def state(self):

@@ -1,0 +1,161 @@
+"""GPU adjoint against the FP64 oracle's hand-written transpose (through the C ABI).
+
+The stored state of the library is the post-collision population X_t, so one
+library adjoint step is dL/dX_t = S^T C^T dL/dX_{t+1} with C the collision at
+f_t = pull(X_t) and S the pull streaming; in oracle terms that is
+``stream_adjoint(collide_adjoint(f_t, lam))``.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as oadj
+from oracle import lbm as olbm
+from paper_1601_01237_amd import inputs
+
+from ._gpu_util import rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_state(shape, seed, solid=None):
+    rng = np.random.default_rng(seed)
+    rho = 0.3 + rng.uniform(0.0, 0.7, size=(2,) + shape)
+    u = rng.uniform(-0.05, 0.05, size=(3,) + shape)
+    f = np.stack([olbm.equilibrium(rho[a], u) for a in range(2)])
+    f = f * (1.0 + 0.02 * rng.uniform(-1.0, 1.0, size=f.shape))
+    if solid is not None:
+        f[:, :, solid] = 0.0
+    return f.astype(np.float32).astype(np.float64), rho
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_one_adjoint_step_matches_oracle(lib, walls):
+    from paper_1601_01237_amd.autograd import Reverse, from_plane_major, to_plane_major
+    from paper_1601_01237_amd.sim import Sim
+    say(f"adjoint one step walls={walls}")
+    shape = (7, 9, 70)
+    solid = None
+    if walls:
+        solid = np.zeros(shape, bool)
+        solid[0] = True
+        solid[3, 2:6, 10:30] = True
+    f, rho = _random_state(shape, 1, solid)
+    p = olbm.Params(tau=(0.8, 1.3), G=((0.0, -1.4), (-0.6, 0.0)), rho_wall=(0.15, 0.35))
+    if solid is not None:
+        rho[:, solid] = 0.0
+    sim = Sim(rho, tau=p.tau, G=p.G, rho_wall=p.rho_wall, solid=solid)
+    sim.set_populations(torch.from_numpy(f.astype(np.float32)))
+    lam1 = np.random.default_rng(2).normal(size=f.shape)
+    if solid is not None:
+        lam1[:, :, solid] = 0.0
+    lam1 = lam1.astype(np.float32)
+    rev = Reverse(sim)
+    x_t = sim.state
+    lam_gpu, drho = rev.step(x_t, to_plane_major(torch.from_numpy(lam1).cuda(), shape), want_drho0=True)
+    got = from_plane_major(lam_gpu, shape).cpu().numpy()
+
+    mu, dG, dtau = oadj.collide_adjoint(f, lam1.astype(np.float64), p, solid)
+    want = oadj.stream_adjoint(mu, solid)
+    e = rel_err(got, want)
+    assert e < 1e-5, e
+    d = rev.dparams.cpu().numpy()
+    # Parameter derivatives are sums over cells of terms with random signs
+    # (lam is random here), so the sum is much smaller than its terms; each
+    # FP32 term carries the rounding of f - f^eq.  Bound the error by the sum
+    # of magnitudes of the terms.
+    m = olbm.macroscopic(f, p, solid)
+    scale_tau = [np.sum(np.abs(lam1[a] * (f[a] - olbm.equilibrium(m["rho_s"][a], m["u"])))) / p.tau[a] ** 2
+                 for a in range(2)]
+    assert abs(d[0] - (dG[0, 1] + dG[1, 0])) <= 1e-4 * abs(dG[0, 1] + dG[1, 0]), (d[0], dG)
+    assert abs(d[1] - dtau[0]) <= 1e-6 * scale_tau[0], (d[1], dtau, scale_tau)
+    assert abs(d[2] - dtau[1]) <= 1e-6 * scale_tau[1], (d[2], dtau, scale_tau)
+    drho_want = np.einsum("i,aizyx->azyx", olbm.W, mu)
+    e = rel_err(drho.view(2, *shape).cpu().numpy(), drho_want)
+    assert e < 1e-5, e
+    sim.close()
+
+
+def test_seed_matches_oracle(lib):
+    from paper_1601_01237_amd.autograd import Reverse, from_plane_major
+    from paper_1601_01237_amd.sim import Sim
+    say("adjoint seed")
+    shape = (8, 6, 10)
+    solid = np.zeros(shape, bool)
+    solid[0] = True
+    solid[4, 2, 3] = True
+    rho0 = np.full((2,) + shape, 0.5)
+    rho0[:, solid] = 0.0
+    sim = Sim(rho0, solid=solid)
+    g = np.random.default_rng(3).normal(size=(2,) + shape)
+    g[:, solid] = 0.0
+    lam = Reverse(sim).seed(torch.from_numpy(g))
+    got = from_plane_major(lam, shape).cpu().numpy()
+    lam_f = np.repeat(g[:, None], 19, axis=1)
+    want = oadj.stream_adjoint(lam_f, solid)
+    assert rel_err(got, want) < 1e-6
+    sim.close()
+
+
+def _calibration_inputs(n):
+    rho0 = inputs.sphere_droplet((n, n, n), radius=n * 20.0 / 96.0, seed=0)
+    target = inputs.target_ellipsoid((n, n, n), radius=n * 20.0 / 96.0, seed=1)
+    return rho0, target
+
+
+def test_calibration_gradient_16cube_matches_fp64_oracle(lib):
+    """Differentiation workload scaled to 16^3: 500 steps, checkpoints every 50."""
+    from paper_1601_01237_amd.autograd import LBMFunction
+    say("calibration gradient 16^3 x 500")
+    n, steps, every = 16, 500, 50
+    rho0, target = _calibration_inputs(n)
+    G, tau = -1.0, 1.0
+    r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
+    Gt = torch.tensor(G, dtype=torch.float64, requires_grad=True)
+    Tt = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+    rho = LBMFunction.apply(r0, Gt, Tt, steps, every)
+    tgt = torch.tensor(target, dtype=torch.float32, device="cuda")
+    L = 0.5 * ((rho[0].double() - tgt.double()) ** 2).sum()
+    L.backward()
+
+    p = olbm.Params(tau=(tau, tau), G=((0.0, G), (G, 0.0)))
+    L_ref, dG_ref, dtau_ref, drho0_ref = oadj.loss_and_gradient(rho0, p, steps, target)
+    e_G = abs(float(Gt.grad) - dG_ref) / abs(dG_ref)
+    e_t = abs(float(Tt.grad) - dtau_ref) / abs(dtau_ref)
+    e_r = rel_err(r0.grad.cpu().numpy(), drho0_ref)
+    say(f"16^3 calibration: L {float(L.detach()):.6e} vs {L_ref:.6e}; dL/dG {float(Gt.grad):.6e} vs {dG_ref:.6e} "
+        f"({e_G:.1e}); dL/dtau {float(Tt.grad):.6e} vs {dtau_ref:.6e} ({e_t:.1e}); dL/drho0 {e_r:.1e}")
+    assert abs(float(L) - L_ref) <= 1e-5 * L_ref
+    assert e_G < 1e-3 and e_t < 1e-3 and e_r < 1e-3, (e_G, e_t, e_r)
+
+
+def test_calibration_gradient_against_central_differences(lib):
+    from paper_1601_01237_amd.autograd import LBMFunction
+    say("calibration gradient vs central differences 16^3 x 100")
+    n, steps, every, h = 16, 100, 25, 1e-4
+    rho0, target = _calibration_inputs(n)
+    tgt = torch.tensor(target, dtype=torch.float64, device="cuda")
+
+    def loss(G, tau, r0=None):
+        r = torch.tensor(rho0, device="cuda") if r0 is None else r0
+        rho = LBMFunction.apply(r, torch.tensor(G), torch.tensor(tau), steps, every)
+        return 0.5 * ((rho[0].double() - tgt) ** 2).sum()
+
+    G, tau = -1.0, 1.0
+    r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
+    Gt = torch.tensor(G, dtype=torch.float64, requires_grad=True)
+    Tt = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+    L = 0.5 * ((LBMFunction.apply(r0, Gt, Tt, steps, every)[0].double() - tgt) ** 2).sum()
+    L.backward()
+    with torch.no_grad():
+        fd_G = (float(loss(G + h, tau)) - float(loss(G - h, tau))) / (2 * h)
+        fd_t = (float(loss(G, tau + h)) - float(loss(G, tau - h))) / (2 * h)
+        v = torch.tensor(inputs.uniform_noise(rho0.shape, seed=4), device="cuda")
+        fd_r = (float(loss(G, tau, torch.tensor(rho0, device="cuda") + h * v))
+                - float(loss(G, tau, torch.tensor(rho0, device="cuda") - h * v))) / (2 * h)
+    # FP32 forward: central differences carry ~1e-3 relative noise at h = 1e-4
+    assert abs(float(Gt.grad) - fd_G) <= 1e-2 * abs(fd_G), (float(Gt.grad), fd_G)
+    assert abs(float(Tt.grad) - fd_t) <= 1e-2 * abs(fd_t), (float(Tt.grad), fd_t)
+    ad_r = float((r0.grad * v).sum())
+    assert abs(ad_r - fd_r) <= 1e-2 * abs(fd_r), (ad_r, fd_r)
