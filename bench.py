@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--tile", type=int, default=None, help="tile shape of the step kernel (0..5)")
+    ap.add_argument("--zchunk", type=int, default=None, help="z planes per workgroup (0 = default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -161,7 +163,7 @@ def main():
     shape = (n, n, n)
     rho0 = inputs.sphere_droplet(shape, radius=16.0, seed=0)
     print(f"[bench] headline {n}^3 fp32 steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
-    head = run_case(shape, "fp32", args.steps, args.warmup, rho0=rho0)
+    head = run_case(shape, "fp32", args.steps, args.warmup, rho0=rho0, tile=args.tile, zchunk=args.zchunk)
     ncell = head["n"]
     achieved = BYTES_PER_CELL["fp32"] * ncell / (head["ms_per_step"] * 1e-3) / 1e9
     workload = f"{n}^3"

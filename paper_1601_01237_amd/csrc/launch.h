@@ -29,8 +29,8 @@ struct Tiling {
   int blocks;
 };
 
-// Tile shapes: 0 = 64x8, 1 = 64x12, 2 = 32x16, 3 = 32x24, 4 = 64x4 cells.
-constexpr int TILE_SHAPES = 5;
+// Tile shapes: 0 = 64x8, 1 = 64x12, 2 = 32x16, 3 = 128x4, 4 = 64x4, 5 = 256x2 cells.
+constexpr int TILE_SHAPES = 6;
 Tiling make_tiling(const Grid& g, int tile, int zchunk);
 
 // Diagnostic region (device-side floats).

@@ -423,9 +423,9 @@ struct Shape {
   static constexpr int EY = ROWS + 2;
   static constexpr int NH = 2 * EX + 2 * ROWS;
   static constexpr int NT = NOWN + 64 * HW;
+  static constexpr int HPL = (NH + 64 * HW - 1) / (64 * HW);  // halo cells per halo lane
   static constexpr int SLOTS = 5;
   static_assert(NOWN % 64 == 0, "own lanes fill whole waves");
-  static_assert(NH <= 64 * HW, "one halo cell per halo lane");
 };
 
 // Ring position of halo cell h: bottom row, top row, left column, right column.
@@ -628,42 +628,54 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
     }
   } else {
     // ----------------------------------------------------------- halo waves
-    const int h = tid - Sh::NOWN;
-    const bool has = h < Sh::NH;
-    int hx = 0, hy = 0;
-    halo_pos<BXT, ROWS>(has ? h : 0, hx, hy);
-    const Column hcol = make_column<T>(x0 + hx, y0 + hy, g);
-    const uint32_t hcol_off = (hcol.y[1] + hcol.x[1]) / static_cast<uint32_t>(sizeof(T));
-    const int hat = (hy + 1) * EX + hx + 1;
+    // Halo lane l owns ring cells l, l + 64 HW, l + 128 HW, ... (HPL of them).
+    const int hl = tid - Sh::NOWN;
+    int hat[Sh::HPL];
+    Column hcol[Sh::HPL];
+    uint32_t hcol_off[Sh::HPL];
+    bool has[Sh::HPL];
+#pragma unroll
+    for (int j = 0; j < Sh::HPL; ++j) {
+      const int h = hl + j * 64 * HW;
+      has[j] = h < Sh::NH;
+      int hx = 0, hy = 0;
+      halo_pos<BXT, ROWS>(has[j] ? h : 0, hx, hy);
+      hcol[j] = make_column<T>(x0 + hx, y0 + hy, g);
+      hcol_off[j] = (hcol[j].y[1] + hcol[j].x[1]) / static_cast<uint32_t>(sizeof(T));
+      hat[j] = (hy + 1) * EX + hx + 1;
+    }
 
     auto halo_plane = [&](int k) {
       const int p = z0 - 1 + k;
       const int zw = wrap(p, g.nz);
-      uint32_t hl = 0;
-      if constexpr (WALLS) hl = io.links[static_cast<uint32_t>(zw) * g.nxy + hcol_off];
-      float2 r;
-      if (WALLS && (hl & 1u)) {
-        r = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
-      } else {
-        __amdgpu_buffer_rsrc_t rz[3];
-        rz[0] = plane_rsrc<T>(io.src, wrap(p - 1, g.nz), g);
-        rz[1] = plane_rsrc<T>(io.src, zw, g);
-        rz[2] = plane_rsrc<T>(io.src, wrap(p + 1, g.nz), g);
-        float hf[2][Q];
-        pull<S, WALLS>(rz, ppb, hcol, hl, ws, hf);
-        r = make_float2(sum19(hf[0]), sum19(hf[1]));
+      __amdgpu_buffer_rsrc_t rz[3];
+      rz[0] = plane_rsrc<T>(io.src, wrap(p - 1, g.nz), g);
+      rz[1] = plane_rsrc<T>(io.src, zw, g);
+      rz[2] = plane_rsrc<T>(io.src, wrap(p + 1, g.nz), g);
+      const int sl = k % 5;
+#pragma unroll
+      for (int j = 0; j < Sh::HPL; ++j) {
+        if (!has[j]) continue;
+        uint32_t lk = 0;
+        if constexpr (WALLS) lk = io.links[static_cast<uint32_t>(zw) * g.nxy + hcol_off[j]];
+        float2 r;
+        if (WALLS && (lk & 1u)) {
+          r = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
+        } else {
+          float hf[2][Q];
+          pull<S, WALLS>(rz, ppb, hcol[j], lk, ws, hf);
+          r = make_float2(sum19(hf[0]), sum19(hf[1]));
+        }
+        ring[sl * PLANE + hat[j]] = r;
       }
-      ring[(k % 5) * PLANE + hat] = r;
     };
 
     // Planes p_0 .. p_2 before the first barrier (k = 1), then p_{k+2}
     // right after barrier k: one plane ahead of the own waves.
-    if (has) {
-      for (int k = 0; k <= min(2, kmax); ++k) halo_plane(k);
-    }
+    for (int k = 0; k <= min(2, kmax); ++k) halo_plane(k);
     for (int k = 1; k <= kmax; ++k) {
       __syncthreads();
-      if (has && k + 2 <= kmax) halo_plane(k + 2);
+      if (k + 2 <= kmax) halo_plane(k + 2);
     }
   }
 
@@ -684,7 +696,7 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
 struct TileShape {
   int bx, rows, hw;
 };
-constexpr TileShape TILES[] = {{64, 8, 3}, {64, 12, 3}, {32, 16, 2}, {32, 24, 2}, {64, 4, 3}};
+constexpr TileShape TILES[] = {{64, 8, 3}, {64, 12, 3}, {32, 16, 2}, {128, 4, 3}, {64, 4, 3}, {256, 2, 3}};
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
 
 Tiling make_tiling(const Grid& g, int tile, int zchunk) {
@@ -733,8 +745,9 @@ static hipError_t launch_tile(const Grid& g, const Phys& ph, const Tiling& t, co
       case 0: return launch_shape<S, WALLS, M, 64, 8, 3>(g, ph, t, io, st);
       case 1: return launch_shape<S, WALLS, M, 64, 12, 3>(g, ph, t, io, st);
       case 2: return launch_shape<S, WALLS, M, 32, 16, 2>(g, ph, t, io, st);
-      case 3: return launch_shape<S, WALLS, M, 32, 24, 2>(g, ph, t, io, st);
+      case 3: return launch_shape<S, WALLS, M, 128, 4, 3>(g, ph, t, io, st);
       case 4: return launch_shape<S, WALLS, M, 64, 4, 3>(g, ph, t, io, st);
+      case 5: return launch_shape<S, WALLS, M, 256, 2, 3>(g, ph, t, io, st);
       default: return hipErrorInvalidValue;
     }
   } else {

@@ -62,20 +62,30 @@ def _two_species(inside, rng, noise=NOISE):
     return np.stack([rho_a, rho_b]).astype(np.float64)
 
 
-def sphere_droplet(shape, radius, seed=0, center=None, noise=NOISE):
+def sphere_droplet(shape, radius, seed=0, center=None, noise=NOISE, width=0.0):
     """One spherical droplet of species A in a periodic box.
 
     A cell (integer centre) is inside iff its minimum-image squared distance to
     ``center`` is below ``radius**2``.  ``center`` defaults to
-    ``(nx/2, ny/2, nz/2)`` given as (x, y, z).  Returns ``rho0``
-    ``(2, nz, ny, nx)`` float64.
+    ``(nx/2, ny/2, nz/2)`` given as (x, y, z).  With ``width`` > 0 the
+    interface is the profile 1/2 (1 - tanh((r - R) / width)) between the two
+    phase densities instead of a step.  Returns ``rho0`` ``(2, nz, ny, nx)``
+    float64.
     """
     nz, ny, nx = shape
     if center is None:
         center = (nx / 2.0, ny / 2.0, nz / 2.0)
     rng = np.random.default_rng(seed)
-    inside = _periodic_dist2(shape, center) < radius * radius
-    return _two_species(inside, rng, noise)
+    d2 = _periodic_dist2(shape, center)
+    if width <= 0.0:
+        return _two_species(d2 < radius * radius, rng, noise)
+    frac = 0.5 * (1.0 - np.tanh((np.sqrt(d2) - radius) / width))
+    rho_a = RHO_OUT + (RHO_IN - RHO_OUT) * frac
+    rho_b = RHO_IN - (RHO_IN - RHO_OUT) * frac
+    if noise:
+        rho_a = rho_a + rng.uniform(-noise, noise, size=shape)
+        rho_b = rho_b + rng.uniform(-noise, noise, size=shape)
+    return np.stack([rho_a, rho_b]).astype(np.float64)
 
 
 def random_droplets(shape, count=64, rmin=8.0, rmax=24.0, seed=0, noise=NOISE):

@@ -119,7 +119,7 @@ class Sim:
         _lib.check("lbm_step", self.lib.lbm_step(self.ctx, int(n)))
 
     def set_tiling(self, tile=0, zchunk=0):
-        """Tile shape of the step kernel (0..4, see lbm_set_tiling) and z planes per workgroup."""
+        """Tile shape of the step kernel (0..5, see lbm_set_tiling) and z planes per workgroup."""
         _lib.check("lbm_set_tiling", self.lib.lbm_set_tiling(self.ctx, int(tile), int(zchunk)))
 
     @property

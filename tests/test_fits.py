@@ -1,0 +1,52 @@
+"""Host-side fits against closed forms (no GPU)."""
+
+import math
+
+import numpy as np
+
+from paper_1601_01237_amd import fits
+
+
+def test_laplace_fit_recovers_exact_line():
+    R = np.array([8.0, 12.0, 16.0, 24.0])
+    sigma = 0.037
+    dp = 2 * sigma / R + 1e-4
+    s, a, b, r2 = fits.laplace_fit(R, dp)
+    assert abs(s - sigma) < 1e-12 and abs(b - 1e-4) < 1e-12 and r2 > 1 - 1e-12
+
+
+def test_equivalent_radius_of_exact_sphere_volume():
+    R = 10.0
+    N = 64 ** 3
+    vol = 4.0 / 3.0 * math.pi * R ** 3
+    mass = 1.2 * vol + 0.05 * (N - vol)
+    assert abs(fits.equivalent_radius(mass, N, 1.2, 0.05) - R) < 1e-12
+
+
+def test_tanh_radius_of_synthetic_profile():
+    shape = (40, 40, 40)
+    center = (20.3, 19.7, 20.1)
+    r = fits.radial_coordinate(shape, center)
+    rho = 0.5 - 0.45 * np.tanh((r - 9.3) / 1.7)
+    R, _ = fits.tanh_radius(rho, center)
+    assert abs(R - 9.3) < 1e-6
+
+
+def test_sphere_fit_and_contact_angle():
+    rng = np.random.default_rng(0)
+    c = np.array([30.0, 31.0, 5.5])
+    rad = 12.0
+    v = rng.normal(size=(500, 3))
+    pts = c + rad * v / np.linalg.norm(v, axis=1, keepdims=True)
+    cc, rr = fits.sphere_fit(pts)
+    assert np.allclose(cc, c, atol=1e-9) and abs(rr - rad) < 1e-9
+    # wall at the centre height: hemisphere, 90 degrees
+    assert abs(fits.contact_angle(cc, rr, 5.5) - 90.0) < 1e-6
+    # wall below the centre: more than a hemisphere sits above it
+    theta = fits.contact_angle(cc, rr, 5.5 - 6.0)
+    assert abs(theta - math.degrees(math.acos(-0.5))) < 1e-6
+
+
+def test_drift_velocity_wraps_periodically():
+    v, d = fits.drift_velocity([1.0, 5.0, 2.0], [99.0, 5.0, 2.0], 10, lengths=(100.0, 100.0, 50.0))
+    assert abs(v - 0.2) < 1e-12 and abs(d[0] + 0.2) < 1e-12

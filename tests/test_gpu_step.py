@@ -64,7 +64,8 @@ def test_c1_droplet_32cube(lib, steps):
 
 @pytest.mark.parametrize("shape,tile", [((11, 13, 70), 0), ((3, 4, 5), 0), ((2, 1, 3), 0), ((9, 17, 130), 0),
                                         ((11, 29, 70), 1), ((11, 29, 70), 2), ((11, 29, 70), 3),
-                                        ((11, 29, 70), 4), ((5, 3, 40), 2)])
+                                        ((11, 29, 70), 4), ((5, 3, 40), 2), ((11, 29, 300), 5),
+                                        ((6, 7, 130), 3)])
 def test_ragged_grids(lib, shape, tile):
     say(f"ragged {shape} tile {tile}")
     rng = np.random.default_rng(3)
@@ -153,7 +154,7 @@ def test_tiling_invariance_bitwise(lib, walls):
         rho0[:, solid] = 0.0
     p = olbm.Params(tau=(0.8, 0.8), G=((0.0, -1.5), (-1.5, 0.0)), rho_wall=(0.1, 0.2))
     ref = _state_after(rho0, p, 7, 0, 0, solid)
-    for tile, zc in [(4, 0), (0, 1), (1, 3), (2, 20), (3, 7), (2, 2), (4, 5)]:
+    for tile, zc in [(4, 0), (0, 1), (1, 3), (2, 20), (3, 7), (2, 2), (4, 5), (5, 0), (5, 3), (3, 1)]:
         got = _state_after(rho0, p, 7, tile, zc, solid)
         diff = float((got - ref).abs().max())
         assert torch.equal(got, ref), (tile, zc, diff)
