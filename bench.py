@@ -88,6 +88,35 @@ def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1
     return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, nonfinite=diag["nonfinite"], n=n)
 
 
+def adjoint_cost(n=96, steps=20):
+    """Forward step vs one reverse step on the differentiation workload (n^3, R = 20 n / 96)."""
+    import torch
+    from paper_1601_01237_amd import inputs
+    from paper_1601_01237_amd.autograd import Reverse
+    from paper_1601_01237_amd.sim import Sim
+    rho0 = inputs.sphere_droplet((n, n, n), radius=20.0 * n / 96.0, seed=0)
+    sim = Sim(rho0, tau=(1.0, 1.0), G=-1.0)
+    fwd_ms = time_steps(sim, steps, 5)
+    rev = Reverse(sim)
+    grad = torch.ones((2, n, n, n), dtype=torch.float32, device=sim.device)
+    lam = rev.seed(grad)
+    x_t = sim.state.clone()
+    lam, _ = rev.step(x_t, lam)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(sim.stream)
+    for _ in range(steps):
+        lam, _ = rev.step(x_t, lam)
+    end.record(sim.stream)
+    torch.cuda.synchronize()
+    adj_ms = start.elapsed_time(end) / steps
+    sim.close()
+    return dict(forward_ms=round(fwd_ms, 4), adjoint_step_ms=round(adj_ms, 4),
+                ratio=round(adj_ms / fwd_ms, 3),
+                ratio_with_recompute=round((adj_ms + fwd_ms) / fwd_ms, 3))
+
+
 def copy_ceiling(gib=2.0, reps=10):
     """Read + write bandwidth of the library's plain streaming copy (GB/s)."""
     import ctypes
@@ -187,6 +216,8 @@ def main():
         fluid = int((~solid).sum())
         r["mlups_fluid_only"] = fluid / (r["ms_per_step"] * 1e-3) / 1e6
         extra["384x192x192_walls_fp32"] = {k: round(v, 3) for k, v in r.items() if k != "n"}
+        print("[bench] adjoint 96^3", file=sys.stderr, flush=True)
+        extra["adjoint_96^3"] = adjoint_cost()
 
     cpu = None
     if not args.no_cpu:
@@ -214,7 +245,7 @@ def main():
                      "algorithmic_bytes_per_cell": BYTES_PER_CELL["fp32"],
                      "copy_ceiling_gbs": round(ceiling, 1),
                      "frac_of_copy_ceiling": round(achieved / ceiling, 4),
-                     "kernel": "march_kernel<F32, no walls, Step, 8 rows>"},
+                     "kernel": "march_kernel<F32, no walls, Step, 128x4 tile>"},
         "cpu_baseline": cpu,
         "extra": extra,
     }

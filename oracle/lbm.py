@@ -284,23 +284,35 @@ def _round_bf16(x64):
     return bits.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def _round_to(dev, storage):
+    if storage == "fp32":
+        return dev.astype(np.float32).astype(np.float64)
+    if storage == "fp16":
+        return dev.astype(np.float16).astype(np.float64)
+    if storage == "bf16":
+        return _round_bf16(dev)
+    raise ValueError(storage)
+
+
 def round_storage(fstar, storage, rho_shift):
-    """Store f*_i^a as round(f*_i^a - w_i rho_shift^a) and read it back in FP64."""
+    """Pass post-collision populations through the shifted 16-bit storage form.
+
+    The storage rule of this build (not the paper's): each moving population
+    is stored as round(f*_i^a - w_i rho_shift^a); the rest population is stored
+    as round(rho^a - sum_{i>0} decoded_i - w_0 rho_shift^a), so that the
+    decoded populations of a cell sum to its density up to one rounding.
+    Returns the decoded values in FP64.
+    """
     if storage == "fp64":
         return fstar
     out = np.empty_like(fstar)
     for a in range(2):
         shift = W[:, None, None, None] * rho_shift[a]
-        dev = fstar[a] - shift
-        if storage == "fp32":
-            r = dev.astype(np.float32).astype(np.float64)
-        elif storage == "fp16":
-            r = dev.astype(np.float16).astype(np.float64)
-        elif storage == "bf16":
-            r = _round_bf16(dev)
-        else:
-            raise ValueError(storage)
-        out[a] = r + shift
+        moving = _round_to(fstar[a, 1:] - shift[1:], storage) + shift[1:]
+        rho = fstar[a].sum(axis=0)
+        rest = _round_to(rho - moving.sum(axis=0) - shift[0], storage) + shift[0]
+        out[a, 1:] = moving
+        out[a, 0] = rest
     return out
 
 

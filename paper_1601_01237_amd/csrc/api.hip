@@ -7,7 +7,7 @@
 #include <cstdlib>
 #include <new>
 
-#include "../../include/lbm.h"
+#include "lbm.h"
 #include "launch.h"
 
 using namespace lbm;
@@ -32,9 +32,14 @@ size_t elem_size(Storage s) { return s == Storage::F32 ? 4 : 2; }
 
 lbm_status from_hip(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 
-// Step kernel: the selected tile shape; diagnostics and adjoint: shape 0.
-Tiling step_tiling(const lbm_ctx* c) { return make_tiling(c->g, c->tile, c->zchunk); }
+// Step kernel: the selected tile shape (automatic: 128x4 without walls, 64x8
+// with walls, the faster of the shapes measured on each); diagnostics: shape 0.
+Tiling step_tiling(const lbm_ctx* c) {
+  const int tile = c->tile >= 0 ? c->tile : auto_tile(c->g, c->links != nullptr);
+  return make_tiling(c->g, tile, c->zchunk);
+}
 Tiling aux_tiling(const lbm_ctx* c) { return make_tiling(c->g, 0, 0); }
+Tiling adjoint_tiling(const lbm_ctx* c) { return make_tiling(c->g, ADJOINT_TILE, 0); }
 
 lbm_status ensure_partials(lbm_ctx* c, size_t need) {
   if (need <= c->partials_cap) return LBM_OK;
@@ -120,7 +125,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
   c->links = nullptr;
   c->stream = static_cast<hipStream_t>(stream);
   c->t = 0;
-  c->tile = 0;
+  c->tile = -1;
   c->zchunk = 0;
   c->partials = nullptr;
   c->partials_cap = 0;
@@ -229,7 +234,7 @@ lbm_status lbm_set_time(lbm_ctx* c, int64_t t) {
 }
 
 lbm_status lbm_set_tiling(lbm_ctx* c, int32_t tile, int32_t zchunk) {
-  if (!c || tile < 0 || tile >= TILE_SHAPES || zchunk < 0) return LBM_EINVAL;
+  if (!c || tile < -1 || tile >= TILE_SHAPES || zchunk < 0) return LBM_EINVAL;
   c->tile = tile;
   c->zchunk = zchunk;
   return LBM_OK;
@@ -237,7 +242,7 @@ lbm_status lbm_set_tiling(lbm_ctx* c, int32_t tile, int32_t zchunk) {
 
 size_t lbm_adjoint_work_bytes(const lbm_ctx* c) {
   if (!c) return 0;
-  const Tiling t = aux_tiling(c);
+  const Tiling t = adjoint_tiling(c);
   const size_t fields = static_cast<size_t>(c->g.n) * 11 * sizeof(float);
   const size_t parts = static_cast<size_t>(t.blocks > 0 ? t.blocks : 0) * 3 * sizeof(double);
   return ((fields + 255) / 256) * 256 + parts;
@@ -250,7 +255,7 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, fl
   if (lam_in == lam_out || static_cast<const void*>(lam_in) == x_t || static_cast<const void*>(lam_out) == x_t)
     return LBM_EINVAL;
   if (c->storage != Storage::F32) return LBM_ENOTSUP;
-  const Tiling t = aux_tiling(c);
+  const Tiling t = adjoint_tiling(c);
   if (t.blocks <= 0) return LBM_ENOTSUP;
   float* m = static_cast<float*>(work);
   float* sbar = m + 5 * c->g.n;

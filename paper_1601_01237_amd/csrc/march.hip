@@ -1,30 +1,30 @@
 // Fused z-marching kernels of the two-component D3Q19 step (gfx950).
 //
-// One workgroup owns a tile of 64 x ROWS cells in the x-y plane and marches
+// One workgroup owns a tile of BX x ROWS cells in the x-y plane and marches
 // up a chunk of z planes.  For each new plane it pulls the 38 populations of
 // its cells (Eq. 1 in pull form, with halfway bounce-back at walls, Sec. 4)
-// and reduces the species densities rho^A, rho^B (Eq. 4) into a 4-slot LDS
-// ring that also holds a one-cell halo of the tile.  The halo densities are
-// recomputed from the populations around the tile, so no density field ever
-// travels through HBM.  Once plane z+1 is in the ring, plane z has every
-// neighbour density the Shan-Chen sum of Eq. (7) needs, and the cell update
-// (Eqs. 2-9) runs from the populations the thread kept in registers.
+// and reduces the species densities rho^A, rho^B (Eq. 4) into a 5-slot LDS
+// ring that also holds a one-cell halo of the tile.  Separate halo waves
+// recompute the halo densities from the populations around the tile, one
+// plane ahead of the owner waves, so no density field ever travels through
+// HBM.  Once plane z+1 is in the ring, plane z has every neighbour density the
+// Shan-Chen sum of Eq. (7) needs, and the cell update (Eqs. 2-9) runs from the
+// populations the owner thread kept in registers.
 //
 // The same march serves three bodies:
 //   Step     collide and store X_{t+1}(x) = f*(x)  (post-collision state);
 //   Moments  rho^a and u_F fields plus FP64 per-workgroup diagnostic sums;
 //   Adjoint  per-cell transposed collision (see below) for one reverse step.
 //
-// Memory layout: SoA X[a][i][z][y][x], x fastest, so each population load of
-// a 64-wide row is one contiguous 256-byte run (FP32).  Blocks are remapped
+// Memory layout: plane-major X[z][a][i][y][x], x fastest, so each population
+// load of a 64-wide row is one contiguous 256-byte run (FP32) and one z plane
+// of all 38 populations is one contiguous block.  Blocks are remapped
 // so that the tiles dispatched to one XCD (block id mod 8) are contiguous in
 // x and y and share that XCD's L2 for the halo re-reads.
 
 #include "launch.h"
 
 namespace lbm {
-
-constexpr int BX = 64;
 
 // Tile index of a block: dispatch sends block b to XCD b % 8, so give each
 // XCD a contiguous range of tiles.
@@ -84,12 +84,17 @@ __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, u
   }
 }
 
+// Stores carry the non-temporal hint: the new state is not read again in this
+// step, so it should not displace the lines neighbouring workgroups still
+// need for their halo.
+constexpr int STORE_NT = 2;
+
 template <typename T>
 __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   if constexpr (sizeof(T) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, STORE_NT);
   } else {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, STORE_NT);
   }
 }
 
@@ -251,7 +256,6 @@ __device__ __forceinline__ void collide(float f[2][Q], const Local& L, const Phy
     om1[s] = ph.omega[s] - 1.0f;
     keep[s] = 1.0f - ph.omega[s];
     r[s] = L.rho[s];
-    f[s][0] = fmaf(keep[s], f[s][0], (W0 * r[s]) * fmaf(om1[s], au, av[s]));
   }
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
@@ -269,6 +273,18 @@ __device__ __forceinline__ void collide(float f[2][Q], const Local& L, const Phy
       f[s][2 * k + 1] = fmaf(keep[s], f[s][2 * k + 1], wr * (ke + ko));
       f[s][2 * k + 2] = fmaf(keep[s], f[s][2 * k + 2], wr * (ke - ko));
     }
+  }
+  // Collision and forcing leave rho^a unchanged (sum_i w_i P_i(v) = 1).  The
+  // rest population is written as the remainder rho^a - sum_{i>0} f*_i, which
+  // equals (1 - w) f_0 + w_0 rho^a [(w - 1) P_0(u) + P_0(v^a)] in exact
+  // arithmetic; in FP32 it keeps the rounding of the weights 1/3, 1/18, 1/36
+  // (their FP32 values sum to 1 + 3e-8) from creating mass every step.
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    float moving = f[s][1];
+#pragma unroll
+    for (int i = 2; i < Q; ++i) moving += f[s][i];
+    f[s][0] = r[s] - moving;
   }
 }
 
@@ -532,11 +548,24 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
                 const __amdgpu_buffer_rsrc_t rd = plane_rsrc<T>(io.dst, zc, g);
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
+                  if constexpr (Tr::shifted) {
+                    // 16-bit storage: round the 18 moving populations, then
+                    // store the rest population so that the stored values
+                    // decode to a sum as close to rho^a as the format allows.
+                    float decoded = 0.0f;
 #pragma unroll
-                  for (int i = 0; i < Q; ++i) {
-                    float v = cur[s][i];
-                    if constexpr (Tr::shifted) v -= ws[s][i == 0 ? 0 : (i <= 6 ? 1 : 2)];
-                    buf_store<T>(Tr::encode(v), rd, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
+                    for (int i = 1; i < Q; ++i) {
+                      const float w_s = ws[s][i <= 6 ? 1 : 2];
+                      const T q = Tr::encode(cur[s][i] - w_s);
+                      decoded += Tr::decode(q) + w_s;
+                      buf_store<T>(q, rd, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
+                    }
+                    const T q0 = Tr::encode((cur_rho[s] - decoded) - ws[s][0]);
+                    buf_store<T>(q0, rd, col_b, static_cast<uint32_t>(s * Q) * ppb);
+                  } else {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i)
+                      buf_store<T>(Tr::encode(cur[s][i]), rd, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
                   }
                 }
               }
@@ -711,12 +740,12 @@ Tiling make_tiling(const Grid& g, int tile, int zchunk) {
   t.tiles_y = (g.ny + sh.rows - 1) / sh.rows;
   const long long txy = static_cast<long long>(t.tiles_x) * t.tiles_y;
   if (zchunk <= 0) {
-    // One workgroup fills a CU (11 waves); march 16 to 32 planes so that the
-    // two planes each workgroup re-reads at its ends cost at most 1/8, with
-    // about one workgroup per CU (256 CUs) per round.
-    long long zc = (static_cast<long long>(g.nz) * txy + 255) / 256;
+    // One workgroup fills a CU; march 16 to 64 planes, so that the two planes
+    // each workgroup re-reads at the ends of its column cost at most 1/8, with
+    // at least about two workgroups per CU (256 CUs) over the launch.
+    long long zc = (static_cast<long long>(g.nz) * txy + 511) / 512;
     if (zc < 16) zc = 16;
-    if (zc > 32) zc = 32;
+    if (zc > 64) zc = 64;
     if (zc > g.nz) zc = g.nz;
     zchunk = static_cast<int>(zc);
   }
@@ -726,6 +755,28 @@ Tiling make_tiling(const Grid& g, int tile, int zchunk) {
   const long long nb = txy * t.tiles_z;
   t.blocks = nb > 0x7fffffffLL ? -1 : static_cast<int>(nb);
   return t;
+}
+
+int auto_tile(const Grid& g, bool walls) {
+  // Widest rows first: 128-lane rows read whole 512-byte population rows.
+  // A shape wins only by padding the x-y plane less (lanes past nx or ny do no
+  // work).  The (128, 4) shape keeps too few registers for the wall path.
+  static constexpr int open_order[] = {3, 0, 2};
+  static constexpr int wall_order[] = {0, 2};
+  const int* order = walls ? wall_order : open_order;
+  const int count = walls ? 2 : 3;
+  int best = order[0];
+  long long best_cells = -1;
+  for (int k = 0; k < count; ++k) {
+    const TileShape sh = TILES[order[k]];
+    const long long cells = static_cast<long long>((g.nx + sh.bx - 1) / sh.bx) * sh.bx *
+                            (static_cast<long long>((g.ny + sh.rows - 1) / sh.rows) * sh.rows);
+    if (best_cells < 0 || cells < best_cells) {
+      best_cells = cells;
+      best = order[k];
+    }
+  }
+  return best;
 }
 
 template <Storage S, bool WALLS, Mode M, int BXT, int ROWS, int HW>
@@ -750,10 +801,15 @@ static hipError_t launch_tile(const Grid& g, const Phys& ph, const Tiling& t, co
       case 5: return launch_shape<S, WALLS, M, 256, 2, 3>(g, ph, t, io, st);
       default: return hipErrorInvalidValue;
     }
-  } else {
-    // Diagnostics and the adjoint use one shape (tile 0).
+  } else if constexpr (M == Mode::Moments) {
+    // Diagnostics use one shape (tile 0).
     if (t.tile != 0) return hipErrorInvalidValue;
     return launch_shape<S, WALLS, M, 64, 8, 3>(g, ph, t, io, st);
+  } else {
+    // The adjoint body holds a third set of 38 values (dL/dX at the cell):
+    // the 64x4 shape (7 waves) leaves it enough registers not to spill.
+    if (t.tile != ADJOINT_TILE) return hipErrorInvalidValue;
+    return launch_shape<S, WALLS, M, 64, 4, 3>(g, ph, t, io, st);
   }
 }
 

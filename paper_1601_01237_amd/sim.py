@@ -93,7 +93,7 @@ class Sim:
                 _ptr(self.solid_dev), _ptr(self.rho0_dev), C.c_void_p(self.stream.cuda_stream)))
         self.ctx = ctx
         if tile is not None or zchunk is not None:
-            self.set_tiling(tile or 0, zchunk or 0)
+            self.set_tiling(-1 if tile is None else tile, zchunk or 0)
 
     # -- lifetime --------------------------------------------------------------
     def close(self):
@@ -118,8 +118,8 @@ class Sim:
     def step(self, n=1):
         _lib.check("lbm_step", self.lib.lbm_step(self.ctx, int(n)))
 
-    def set_tiling(self, tile=0, zchunk=0):
-        """Tile shape of the step kernel (0..5, see lbm_set_tiling) and z planes per workgroup."""
+    def set_tiling(self, tile=-1, zchunk=0):
+        """Tile shape of the step kernel (-1 = automatic, 0..5, see lbm_set_tiling) and z planes per workgroup."""
         _lib.check("lbm_set_tiling", self.lib.lbm_set_tiling(self.ctx, int(tile), int(zchunk)))
 
     @property

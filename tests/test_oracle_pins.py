@@ -427,5 +427,14 @@ def test_fp16_storage_round_trip_bound():
     shift = (0.3, 0.6)
     r = lbm.round_storage(fstar, "fp16", shift)
     dev = np.abs(fstar - W[None, :, None, None, None] * np.array(shift)[:, None, None, None, None])
-    # round to nearest: error at most half an fp16 ulp of the stored deviation
-    assert np.all(np.abs(r - fstar) <= dev * 2.0 ** -11 + 2.0 ** -25)
+    # moving populations, round to nearest: at most half an fp16 ulp of the
+    # stored deviation
+    assert np.all(np.abs(r - fstar)[:, 1:] <= dev[:, 1:] * 2.0 ** -11 + 2.0 ** -25)
+    # rest population absorbs the others' rounding: the decoded populations
+    # sum to the density up to one rounding of the stored rest deviation
+    rest_dev = np.abs(r[:, 0] - W[0] * np.array(shift)[:, None, None, None])
+    rho = fstar.sum(axis=1)
+    assert np.all(np.abs(r.sum(axis=1) - rho) <= rest_dev * 2.0 ** -11 + 2.0 ** -25)
+    # and the rounding errors do not all point the same way: the mass error is
+    # far below the sum of the per-population bounds
+    assert np.abs(r.sum(axis=1) - rho).max() < 0.1 * (dev * 2.0 ** -11).sum(axis=1).max()
