@@ -18,7 +18,6 @@ events on the stream the kernel runs on.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -34,14 +33,6 @@ BYTES_PER_CELL = {"fp32": 304, "fp16": 152, "bf16": 152}
 ALGO_BYTES_NOTE = "2 species x 19 populations x element size, read + write, per cell-step"
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for name in ("march.hip", "lattice.h", "launch.h"):
-        with open(os.path.join(ROOT, "paper_1601_01237_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def stored_traffic(workload, storage):
     """HBM bytes per launch from committed rocprofv3 counter runs, if the kernel is unchanged."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -54,6 +45,7 @@ def stored_traffic(workload, storage):
         return None
     key = f"{workload}:{storage}"
     ent = rec.get(key)
+    from paper_1601_01237_amd.profiling import kernel_source_hash
     if not ent or ent.get("kernel_hash") != kernel_source_hash():
         return None
     return ent.get("bytes_per_launch")
@@ -88,8 +80,11 @@ def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1
     return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, nonfinite=diag["nonfinite"], n=n)
 
 
-def adjoint_cost(n=96, steps=20):
-    """Forward step vs one reverse step on the differentiation workload (n^3, R = 20 n / 96)."""
+def adjoint_cost(n=96, steps=20, adjoint_tile=None):
+    """Forward step vs one reverse step on the differentiation workload (n^3, R = 20 n / 96).
+
+    Both at the library's automatic tiling unless ``adjoint_tile`` names the
+    adjoint march's shape (0, 2 or 4)."""
     import torch
     from paper_1601_01237_amd import inputs
     from paper_1601_01237_amd.autograd import Reverse
@@ -97,6 +92,8 @@ def adjoint_cost(n=96, steps=20):
     rho0 = inputs.sphere_droplet((n, n, n), radius=20.0 * n / 96.0, seed=0)
     sim = Sim(rho0, tau=(1.0, 1.0), G=-1.0)
     fwd_ms = time_steps(sim, steps, 5)
+    if adjoint_tile is not None:
+        sim.set_tiling(adjoint_tile, 0)
     rev = Reverse(sim)
     grad = torch.ones((2, n, n, n), dtype=torch.float32, device=sim.device)
     lam = rev.seed(grad)

@@ -172,9 +172,11 @@ lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
 /* Tiling of the fused step kernel: workgroup tile shape and the number of z
  * planes each workgroup marches through (>= 1; 0 picks a default from the
  * grid).  Shapes (cells in x by y): 0 = 64x8, 1 = 64x12, 2 = 32x16,
- * 3 = 128x4, 4 = 64x4, 5 = 256x2; -1 (the default) = 128x4 without walls and
- * 64x8 with walls.  Results do not depend on this choice (bitwise).
- * Host-side setting; diagnostics and the adjoint use fixed shapes. */
+ * 3 = 128x4, 4 = 64x4, 5 = 256x2; -1 (the default) picks, among 128x4, 64x8
+ * and 32x16 (64x8 and 32x16 with walls), the one that pads the x-y plane
+ * least, the wider on a tie.  Results do not depend on this choice (bitwise).
+ * The adjoint march uses the same setting when it is 0, 2 or 4, else the
+ * automatic choice with walls; diagnostics use 64x8.  Host-side setting. */
 lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t tile, int32_t zchunk);
 
 /* ---- Adjoint (reverse mode) of one step, FP32 storage only ------------

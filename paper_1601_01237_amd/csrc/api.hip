@@ -39,7 +39,10 @@ Tiling step_tiling(const lbm_ctx* c) {
   return make_tiling(c->g, tile, c->zchunk);
 }
 Tiling aux_tiling(const lbm_ctx* c) { return make_tiling(c->g, 0, 0); }
-Tiling adjoint_tiling(const lbm_ctx* c) { return make_tiling(c->g, ADJOINT_TILE, 0); }
+Tiling adjoint_tiling(const lbm_ctx* c) {
+  const int tile = adjoint_shape(c->tile) ? c->tile : auto_tile(c->g, true);
+  return make_tiling(c->g, tile, c->tile == tile ? c->zchunk : 0);
+}
 
 lbm_status ensure_partials(lbm_ctx* c, size_t need) {
   if (need <= c->partials_cap) return LBM_OK;

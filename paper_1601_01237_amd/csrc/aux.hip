@@ -1,8 +1,9 @@
 // One-thread-per-cell kernels around the fused march: initial state, wall
 // link masks, conversion between stored and pre-collision populations,
-// deterministic reduction of per-workgroup partial sums and the two
-// neighbour passes of the adjoint step.
+// deterministic reduction of per-workgroup partial sums and the reference
+// copy kernel.
 
+#include "buffer.h"
 #include "launch.h"
 
 namespace lbm {
@@ -62,11 +63,6 @@ __global__ void links_kernel(const Grid g, const uint8_t* __restrict__ solid, ui
   }
 }
 
-__device__ __forceinline__ bool is_solid(const uint32_t* links, uint64_t c) { return links && (links[c] & 1u); }
-// Neighbour x + c_i is solid: bit opp(i) of x.
-__device__ __forceinline__ bool ahead_solid(const uint32_t* links, uint64_t c, int i) {
-  return links && ((links[c] >> opp(i)) & 1u);
-}
 
 // Stored state whose pull at every fluid cell is f_i = w_i rho0 (rest state).
 template <Storage S>
@@ -170,146 +166,6 @@ __global__ void finalize_kernel(const double* __restrict__ partials, int blocks,
   (void)is_max_dev;
 }
 
-// Lane of a 3-D launch (x fastest): block (bx, y, z), 64 lanes along x.  The
-// wrapped coordinates of the +-1 neighbours come from compares, not division.
-struct Cell3 {
-  int x, y, z;
-  int xm, xp, ym, yp, zm, zp;
-  bool valid;
-};
-
-__device__ __forceinline__ Cell3 cell3(const Grid& g) {
-  Cell3 c;
-  c.x = blockIdx.x * blockDim.x + threadIdx.x;
-  c.y = blockIdx.y;
-  c.z = blockIdx.z;
-  c.valid = c.x < g.nx;
-  c.xm = c.x == 0 ? g.nx - 1 : c.x - 1;
-  c.xp = c.x >= g.nx - 1 ? 0 : c.x + 1;
-  c.ym = c.y == 0 ? g.ny - 1 : c.y - 1;
-  c.yp = c.y == g.ny - 1 ? 0 : c.y + 1;
-  c.zm = c.z == 0 ? g.nz - 1 : c.z - 1;
-  c.zp = c.z == g.nz - 1 ? 0 : c.z + 1;
-  return c;
-}
-
-__device__ __forceinline__ int pick(int d, int m, int o, int p) { return d < 0 ? m : (d > 0 ? p : o); }
-
-// Cell index of (x + dx, y + dy, z + dz), |d| <= 1.
-__device__ __forceinline__ uint64_t near(const Cell3& c, int dx, int dy, int dz, const Grid& g) {
-  const uint64_t x = pick(dx, c.xm, c.x, c.xp), y = pick(dy, c.ym, c.y, c.yp), z = pick(dz, c.zm, c.z, c.zp);
-  return (z * g.ny + y) * g.nx + x;
-}
-
-// Plane-major index of population (s, i) at (x + dx, y + dy, z + dz).
-__device__ __forceinline__ uint64_t near_pm(const Cell3& c, int s, int i, int dx, int dy, int dz, const Grid& g) {
-  const uint64_t x = pick(dx, c.xm, c.x, c.xp), y = pick(dy, c.ym, c.y, c.yp), z = pick(dz, c.zm, c.z, c.zp);
-  return ((z * 2 + s) * Q + i) * g.nxy + y * g.nx + x;
-}
-
-// Adjoint, pass 2: A^b(x) = a^b(x) + sum_i w_i c_i . Sbar^b(x - c_i) on fluid x.
-// m holds (a^A, a^B, b_x, b_y, b_z) per cell; a^b is replaced by A^b in place.
-__global__ void __launch_bounds__(64) adjoint_gather_kernel(const Grid g, const uint32_t* __restrict__ links,
-                                                            float* __restrict__ m, const float* __restrict__ sbar) {
-  const Cell3 p = cell3(g);
-  if (!p.valid) return;
-  const uint64_t c = near(p, 0, 0, 0, g);
-  if (is_solid(links, c)) return;
-  float r[2] = {0.f, 0.f};
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const uint64_t at = near(p, -CX[i], -CY[i], -CZ[i], g);
-    const float w = weight(i);
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const float* sb = sbar + static_cast<uint64_t>(3 * s) * g.n;
-      float dot = 0.0f;
-      if (CX[i]) dot += CX[i] * sb[at];
-      if (CY[i]) dot += CY[i] * sb[g.n + at];
-      if (CZ[i]) dot += CZ[i] * sb[2 * g.n + at];
-      r[s] += w * dot;
-    }
-  }
-  m[c] += r[0];
-  m[g.n + c] += r[1];
-}
-
-// Adjoint, pass 3 (transpose of the pull with bounce-back):
-//   lam_t,i(y) = fbar_k(x) with x = y + c_i, k = i, or x = y, k = opp(i) when
-//   y + c_i is a wall, and fbar_k(x) = (1 - w) lam_{t+1},k(x) + A(x) + b(x) . c_k.
-__global__ void __launch_bounds__(64) adjoint_stream_kernel(const Grid g, const Phys ph,
-                                                            const uint32_t* __restrict__ links,
-                                                            const float* __restrict__ lam_in,
-                                                            const float* __restrict__ m, float* __restrict__ lam_out,
-                                                            double* __restrict__ drho0) {
-  const Cell3 p = cell3(g);
-  if (!p.valid) return;
-  const uint64_t c = near(p, 0, 0, 0, g);
-  const bool solid = is_solid(links, c);
-  const uint32_t lk = links ? links[c] : 0u;
-  // A and b of this cell and of its 18 neighbours y + c_i.
-  float A[2][Q], bx[Q], by[Q], bz[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const uint64_t x = near(p, CX[i], CY[i], CZ[i], g);
-    A[0][i] = m[x];
-    A[1][i] = m[g.n + x];
-    bx[i] = m[2 * g.n + x];
-    by[i] = m[3 * g.n + x];
-    bz[i] = m[4 * g.n + x];
-  }
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const float keep = 1.0f - ph.omega[s];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      float v = 0.0f;
-      if (!solid) {
-        const bool back = (i != 0) && ((lk >> opp(i)) & 1u);
-        // b . c_k with c_k = c_i, or -c_i after a bounce
-        const int j = back ? 0 : i;  // the cell x: y + c_i, or y itself (slot 0)
-        const float dot = CX[i] * (back ? bx[0] : bx[i]) + CY[i] * (back ? by[0] : by[i]) +
-                          CZ[i] * (back ? bz[0] : bz[i]);
-        const uint64_t lx = back ? near_pm(p, s, opp(i), 0, 0, 0, g) : near_pm(p, s, i, CX[i], CY[i], CZ[i], g);
-        v = keep * lam_in[lx] + (back ? A[s][0] : A[s][i]) + (i == 0 ? 0.0f : (back ? -dot : dot));
-        (void)j;
-      }
-      lam_out[near_pm(p, s, i, 0, 0, 0, g)] = v;
-    }
-    if (drho0) {
-      double d = 0.0;
-      if (!solid) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) acc += weight(i) * lam_in[near_pm(p, s, i, 0, 0, 0, g)];
-        d = static_cast<double>(keep * acc + A[s][0]);
-      }
-      drho0[s * g.n + c] = d;
-    }
-  }
-}
-
-// dL/dX_T for L(rho(T)): lam_i(y) = grad(y + c_i), or grad(y) if y + c_i is a wall.
-__global__ void __launch_bounds__(64) adjoint_seed_kernel(const Grid g, const uint32_t* __restrict__ links,
-                                                          const float* __restrict__ grad, float* __restrict__ lam) {
-  const Cell3 p = cell3(g);
-  if (!p.valid) return;
-  const uint64_t c = near(p, 0, 0, 0, g);
-  const bool solid = is_solid(links, c);
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      float v = 0.0f;
-      if (!solid) {
-        const uint64_t x = ahead_solid(links, c, i) ? c : near(p, CX[i], CY[i], CZ[i], g);
-        v = grad[s * g.n + x];
-      }
-      lam[near_pm(p, s, i, 0, 0, 0, g)] = v;
-    }
-  }
-}
-
 // Plain streaming copy: the reference for how much read + write bandwidth
 // the memory system delivers to a kernel.  Each lane keeps four independent
 // 16-byte loads in flight per iteration of a grid-stride loop.
@@ -407,24 +263,6 @@ hipError_t launch_finalize(const double* partials, int blocks, int nvals, const 
   return hipGetLastError();
 }
 
-static dim3 grid3(const Grid& g) {
-  return dim3(static_cast<unsigned>((g.nx + 63) / 64), static_cast<unsigned>(g.ny), static_cast<unsigned>(g.nz));
-}
-
-hipError_t launch_adjoint_gather(const Grid& g, const uint32_t* links, float* m, const float* sbar,
-                                 hipStream_t st) {
-  if (g.ny > 65535 || g.nz > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(adjoint_gather_kernel, grid3(g), dim3(64), 0, st, g, links, m, sbar);
-  return hipGetLastError();
-}
-
-hipError_t launch_adjoint_stream(const Grid& g, const Phys& ph, const uint32_t* links, const float* lam_in,
-                                 const float* m, float* lam_out, double* drho0, hipStream_t st) {
-  if (g.ny > 65535 || g.nz > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(adjoint_stream_kernel, grid3(g), dim3(64), 0, st, g, ph, links, lam_in, m, lam_out, drho0);
-  return hipGetLastError();
-}
-
 hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStream_t st) {
   const uint64_t n16 = bytes / 16;
   uint64_t blocks = (n16 + TPB - 1) / TPB;
@@ -432,13 +270,6 @@ hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStr
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(stream_copy_kernel, dim3(static_cast<unsigned>(blocks)), dim3(TPB), 0, st,
                      static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
-  return hipGetLastError();
-}
-
-hipError_t launch_adjoint_seed(const Grid& g, const uint32_t* links, const float* grad_rho, float* lam,
-                               hipStream_t st) {
-  if (g.ny > 65535 || g.nz > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(adjoint_seed_kernel, grid3(g), dim3(64), 0, st, g, links, grad_rho, lam);
   return hipGetLastError();
 }
 

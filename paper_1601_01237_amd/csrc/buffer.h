@@ -1,0 +1,90 @@
+// Addressing helpers shared by the z-marching kernels: XCD-aware block
+// order, periodic wrap, per-column byte offsets and buffer resources over one
+// z plane of the plane-major population layout X[z][a][i][y][x].
+#pragma once
+
+#include "launch.h"
+
+namespace lbm {
+
+// Tile index of a block: dispatch sends block b to XCD b % 8, so give each
+// XCD a contiguous range of tiles.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int k = b & 7, i = b >> 3;
+  return (k < r ? k * (q + 1) : r * (q + 1) + (k - r) * q) + i;
+}
+
+__device__ __forceinline__ int wrap(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// Wrapped coordinates of one cell column (x, y) and of its x/y neighbours,
+// as BYTE offsets inside one population plane (nx * ny elements).
+struct Column {
+  uint32_t x[3];  // (x-1, x, x+1) * sizeof(T)
+  uint32_t y[3];  // ((y-1), y, (y+1)) * nx * sizeof(T)
+};
+
+template <typename T>
+__device__ __forceinline__ Column make_column(int ex, int ey, const Grid& g) {
+  const int gx = wrap(ex, g.nx), gy = wrap(ey, g.ny);
+  const uint32_t sz = sizeof(T);
+  Column c;
+  c.x[0] = (gx == 0 ? g.nx - 1 : gx - 1) * sz;
+  c.x[1] = gx * sz;
+  c.x[2] = (gx == g.nx - 1 ? 0 : gx + 1) * sz;
+  const int ym = gy == 0 ? g.ny - 1 : gy - 1;
+  const int yp = gy == g.ny - 1 ? 0 : gy + 1;
+  c.y[0] = static_cast<uint32_t>(ym) * g.nx * sz;
+  c.y[1] = static_cast<uint32_t>(gy) * g.nx * sz;
+  c.y[2] = static_cast<uint32_t>(yp) * g.nx * sz;
+  return c;
+}
+
+// Buffer resource over the 38 population planes of z plane `zw`
+// (plane-major layout X[z][a][i][y][x]).  Out-of-range offsets read as zero
+// instead of faulting.
+constexpr int RSRC_FLAGS = 0x00020000;  // 32-bit data format, gfx9 family
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* buf, int zw, const Grid& g) {
+  const uint64_t block = static_cast<uint64_t>(2 * Q) * g.nxy * sizeof(T);
+  const char* base = static_cast<const char*>(buf) + static_cast<uint64_t>(zw) * block;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), static_cast<short>(0),
+                                           static_cast<int>(block), RSRC_FLAGS);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+  }
+}
+
+// Stores carry the non-temporal hint: the new state is not read again in this
+// step, so it should not displace the lines neighbouring workgroups still
+// need for their halo.
+constexpr int STORE_NT = 2;
+
+template <typename T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, STORE_NT);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, STORE_NT);
+  }
+}
+
+// Wall links (one 32-bit word per cell): bit i set when x - c_i is a wall
+// cell, bit 0 when x itself is.
+__device__ __forceinline__ bool is_solid(const uint32_t* links, uint64_t c) { return links && (links[c] & 1u); }
+// Neighbour x + c_i is a wall: bit opp(i) of x.
+__device__ __forceinline__ bool ahead_solid(const uint32_t* links, uint64_t c, int i) {
+  return links && ((links[c] >> opp(i)) & 1u);
+}
+
+}  // namespace lbm

@@ -31,7 +31,8 @@ struct Tiling {
 
 // Tile shapes: 0 = 64x8, 1 = 64x12, 2 = 32x16, 3 = 128x4, 4 = 64x4, 5 = 256x2 cells.
 constexpr int TILE_SHAPES = 6;
-constexpr int ADJOINT_TILE = 4;  // shape of the adjoint march
+// Shapes the adjoint march is built for.
+constexpr bool adjoint_shape(int tile) { return tile == 0 || tile == 2 || tile == 4; }
 Tiling make_tiling(const Grid& g, int tile, int zchunk);
 // Shape used when the caller asks for the automatic choice.
 int auto_tile(const Grid& g, bool walls);

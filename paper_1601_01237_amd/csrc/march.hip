@@ -22,81 +22,10 @@
 // so that the tiles dispatched to one XCD (block id mod 8) are contiguous in
 // x and y and share that XCD's L2 for the halo re-reads.
 
+#include "buffer.h"
 #include "launch.h"
 
 namespace lbm {
-
-// Tile index of a block: dispatch sends block b to XCD b % 8, so give each
-// XCD a contiguous range of tiles.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  const int q = nb >> 3, r = nb & 7;
-  const int k = b & 7, i = b >> 3;
-  return (k < r ? k * (q + 1) : r * (q + 1) + (k - r) * q) + i;
-}
-
-__device__ __forceinline__ int wrap(int v, int n) {
-  int r = v % n;
-  return r < 0 ? r + n : r;
-}
-
-// Wrapped coordinates of one cell column (x, y) and of its x/y neighbours,
-// as BYTE offsets inside one population plane (nx * ny elements).
-struct Column {
-  uint32_t x[3];  // (x-1, x, x+1) * sizeof(T)
-  uint32_t y[3];  // ((y-1), y, (y+1)) * nx * sizeof(T)
-};
-
-template <typename T>
-__device__ __forceinline__ Column make_column(int ex, int ey, const Grid& g) {
-  const int gx = wrap(ex, g.nx), gy = wrap(ey, g.ny);
-  const uint32_t sz = sizeof(T);
-  Column c;
-  c.x[0] = (gx == 0 ? g.nx - 1 : gx - 1) * sz;
-  c.x[1] = gx * sz;
-  c.x[2] = (gx == g.nx - 1 ? 0 : gx + 1) * sz;
-  const int ym = gy == 0 ? g.ny - 1 : gy - 1;
-  const int yp = gy == g.ny - 1 ? 0 : gy + 1;
-  c.y[0] = static_cast<uint32_t>(ym) * g.nx * sz;
-  c.y[1] = static_cast<uint32_t>(gy) * g.nx * sz;
-  c.y[2] = static_cast<uint32_t>(yp) * g.nx * sz;
-  return c;
-}
-
-// Buffer resource over the 38 population planes of z plane `zw`
-// (plane-major layout X[z][a][i][y][x]).  Out-of-range offsets read as zero
-// instead of faulting.
-constexpr int RSRC_FLAGS = 0x00020000;  // 32-bit data format, gfx9 family
-
-template <typename T>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* buf, int zw, const Grid& g) {
-  const uint64_t block = static_cast<uint64_t>(2 * Q) * g.nxy * sizeof(T);
-  const char* base = static_cast<const char*>(buf) + static_cast<uint64_t>(zw) * block;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), static_cast<short>(0),
-                                           static_cast<int>(block), RSRC_FLAGS);
-}
-
-template <typename T>
-__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-  } else {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
-  }
-}
-
-// Stores carry the non-temporal hint: the new state is not read again in this
-// step, so it should not displace the lines neighbouring workgroups still
-// need for their halo.
-constexpr int STORE_NT = 2;
-
-template <typename T>
-__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  if constexpr (sizeof(T) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, STORE_NT);
-  } else {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, STORE_NT);
-  }
-}
 
 // Pull of Eq. (1): f_i(x) = X_i(x - c_i), or X_opp(i)(x) when x - c_i is a
 // wall cell (bit i of `links`).  rz[k] covers z plane z - 1 + k; `ppb` is the
@@ -104,31 +33,35 @@ __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_
 // at (19 a + i) * pp.  Every load is scalar resource + scalar population
 // offset + per-lane (y, x) offset.
 template <Storage S, bool WALLS>
-__device__ __forceinline__ void pull(const __amdgpu_buffer_rsrc_t rz[3], uint32_t ppb, const Column& c,
-                                     uint32_t links, const float ws[2][3], float f[2][Q]) {
+__device__ __forceinline__ void pull_species(const __amdgpu_buffer_rsrc_t rz[3], uint32_t ppb, const Column& c,
+                                             uint32_t links, const float ws[3], int s, float f[Q]) {
   using Tr = StorageTraits<S>;
   using T = typename Tr::T;
   const uint32_t own = c.y[1] + c.x[1];
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const uint32_t off = c.y[1 - CY[i]] + c.x[1 - CX[i]];
-      T v;
-      if constexpr (WALLS) {
-        if ((i != 0) && ((links >> i) & 1u)) {
-          v = buf_load<T>(rz[1], own, static_cast<uint32_t>(s * Q + opp(i)) * ppb);
-        } else {
-          v = buf_load<T>(rz[1 - CZ[i]], off, static_cast<uint32_t>(s * Q + i) * ppb);
-        }
+  for (int i = 0; i < Q; ++i) {
+    const uint32_t off = c.y[1 - CY[i]] + c.x[1 - CX[i]];
+    T v;
+    if constexpr (WALLS) {
+      if ((i != 0) && ((links >> i) & 1u)) {
+        v = buf_load<T>(rz[1], own, static_cast<uint32_t>(s * Q + opp(i)) * ppb);
       } else {
         v = buf_load<T>(rz[1 - CZ[i]], off, static_cast<uint32_t>(s * Q + i) * ppb);
       }
-      float x = Tr::decode(v);
-      if constexpr (Tr::shifted) x += ws[s][i == 0 ? 0 : (i <= 6 ? 1 : 2)];
-      f[s][i] = x;
+    } else {
+      v = buf_load<T>(rz[1 - CZ[i]], off, static_cast<uint32_t>(s * Q + i) * ppb);
     }
+    float x = Tr::decode(v);
+    if constexpr (Tr::shifted) x += ws[i == 0 ? 0 : (i <= 6 ? 1 : 2)];
+    f[i] = x;
   }
+}
+
+template <Storage S, bool WALLS>
+__device__ __forceinline__ void pull(const __amdgpu_buffer_rsrc_t rz[3], uint32_t ppb, const Column& c,
+                                     uint32_t links, const float ws[2][3], float f[2][Q]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s) pull_species<S, WALLS>(rz, ppb, c, links, ws[s], s, f[s]);
 }
 
 __device__ __forceinline__ float sum19(const float f[Q]) {
@@ -298,6 +231,7 @@ __device__ __forceinline__ void collide(float f[2][Q], const Local& L, const Phy
 //   a^a = rho_bar^a - u_bar . u / rho,  b = u_bar / rho       (written to mo)
 // and the transpose of the Eq. (7) gather needs Sbar^B = G^{AB} g_bar^A,
 // Sbar^A = G^{BA} g_bar^B (written to sb).  acc += dL/dG (tied), dL/dtau_a.
+// The populations f enter only through dot^a = sum_i lam_i f_i^a.
 __device__ __forceinline__ constexpr int pair_cx(int k) { return (k == 0 || (k >= 3 && k <= 6)) ? 1 : 0; }
 __device__ __forceinline__ constexpr int pair_cy(int k) {
   return (k == 1 || k == 3 || k == 7 || k == 8) ? 1 : (k == 4 ? -1 : 0);
@@ -306,80 +240,91 @@ __device__ __forceinline__ constexpr int pair_cz(int k) {
   return (k == 2 || k == 5 || k == 7) ? 1 : ((k == 6 || k == 8) ? -1 : 0);
 }
 
-__device__ __forceinline__ void adjoint_cell(const float f[2][Q], const float lam[2][Q], const Local& L,
-                                             const Phys& ph, float mo[5], float sb[6], double acc[3]) {
+// Species part of the transposed collision: rho_bar^a, g_bar^a and the
+// species' share of u_bar and of dL/dtau_a, from lam^a (19 values) and dot^a.
+struct AdjointSums {
+  float ubar[3];
+  float rbar[2];
+  float gbar[2][3];
+  float dtau[2];
+};
+
+__device__ __forceinline__ void adjoint_species(int s, float dot, const float lam[Q], const Local& L,
+                                                const Phys& ph, AdjointSums& A) {
   const float* u = L.u;
   const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   float cu[9];
   pair_dots(u[0], u[1], u[2], cu);
-  float ubar[3] = {0.f, 0.f, 0.f};
-  float rbar[2], gbar[2][3];
-  float dtau[2];
+  const float v[3] = {u[0] + L.g[s][0], u[1] + L.g[s][1], u[2] + L.g[s][2]};
+  const float vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  float cv[9];
+  pair_dots(v[0], v[1], v[2], cv);
+  const float om = ph.omega[s];
+  const float om1 = om - 1.0f;
+  const float r = L.rho[s];
+  const float l0 = lam[0] * W0;
+  const float pu0 = 1.0f - 1.5f * uu;
+  const float pv0 = 1.0f - 1.5f * vv;
+  float rb = l0 * (om1 * pu0 + pv0);
+  float bu = 3.0f * l0, bv = 3.0f * l0;
+  float au[3] = {0.f, 0.f, 0.f}, av[3] = {0.f, 0.f, 0.f};
+  float le = l0 * pu0;  // sum_i lam_i E_i(rho^a, u) / rho^a
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const float v[3] = {u[0] + L.g[s][0], u[1] + L.g[s][1], u[2] + L.g[s][2]};
-    const float vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    float cv[9];
-    pair_dots(v[0], v[1], v[2], cv);
-    const float om = ph.omega[s];
-    const float om1 = om - 1.0f;
-    const float r = L.rho[s];
-    const float l0 = lam[s][0] * W0;
-    const float pu0 = 1.0f - 1.5f * uu;
-    const float pv0 = 1.0f - 1.5f * vv;
-    float rb = l0 * (om1 * pu0 + pv0);
-    float bu = 3.0f * l0, bv = 3.0f * l0;
-    float au[3] = {0.f, 0.f, 0.f}, av[3] = {0.f, 0.f, 0.f};
-    float dt = lam[s][0] * (f[s][0] - W0 * r * pu0);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const float w = pair_w(k);
-      const float lp = lam[s][2 * k + 1] * w;
-      const float lm = lam[s][2 * k + 2] * w;
-      const float tu = cu[k] * cu[k];
-      const float tv = cv[k] * cv[k];
-      const float evu = pu0 + 4.5f * tu;
-      const float odu = cu[k] * (3.0f - 4.5f * uu + 4.5f * tu);
-      const float evv = pv0 + 4.5f * tv;
-      const float odv = cv[k] * (3.0f - 4.5f * vv + 4.5f * tv);
-      const float pup = evu + odu, pum = evu - odu;
-      const float pvp = evv + odv, pvm = evv - odv;
-      rb += lp * (om1 * pup + pvp) + lm * (om1 * pum + pvm);
-      const float aue = 3.0f + 13.5f * tu - 4.5f * uu, auo = 9.0f * cu[k];
-      const float ave = 3.0f + 13.5f * tv - 4.5f * vv, avo = 9.0f * cv[k];
-      const float qu = lp * (aue + auo) - lm * (aue - auo);
-      const float qv = lp * (ave + avo) - lm * (ave - avo);
-      bu += lp * (3.0f + auo) + lm * (3.0f - auo);
-      bv += lp * (3.0f + avo) + lm * (3.0f - avo);
-      if (pair_cx(k)) { au[0] += pair_cx(k) * qu; av[0] += pair_cx(k) * qv; }
-      if (pair_cy(k)) { au[1] += pair_cy(k) * qu; av[1] += pair_cy(k) * qv; }
-      if (pair_cz(k)) { au[2] += pair_cz(k) * qu; av[2] += pair_cz(k) * qv; }
-      dt += lam[s][2 * k + 1] * (f[s][2 * k + 1] - w * r * pup) +
-            lam[s][2 * k + 2] * (f[s][2 * k + 2] - w * r * pum);
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      gbar[s][a] = r * (av[a] - v[a] * bv);
-      ubar[a] += r * (om1 * (au[a] - u[a] * bu) + (av[a] - v[a] * bv));
-    }
-    rbar[s] = rb;
-    dtau[s] = om * om * dt;
+  for (int k = 0; k < 9; ++k) {
+    const float w = pair_w(k);
+    const float lp = lam[2 * k + 1] * w;
+    const float lm = lam[2 * k + 2] * w;
+    const float tu = cu[k] * cu[k];
+    const float tv = cv[k] * cv[k];
+    const float evu = pu0 + 4.5f * tu;
+    const float odu = cu[k] * (3.0f - 4.5f * uu + 4.5f * tu);
+    const float evv = pv0 + 4.5f * tv;
+    const float odv = cv[k] * (3.0f - 4.5f * vv + 4.5f * tv);
+    const float pup = evu + odu, pum = evu - odu;
+    const float pvp = evv + odv, pvm = evv - odv;
+    rb += lp * (om1 * pup + pvp) + lm * (om1 * pum + pvm);
+    const float aue = 3.0f + 13.5f * tu - 4.5f * uu, auo = 9.0f * cu[k];
+    const float ave = 3.0f + 13.5f * tv - 4.5f * vv, avo = 9.0f * cv[k];
+    const float qu = lp * (aue + auo) - lm * (aue - auo);
+    const float qv = lp * (ave + avo) - lm * (ave - avo);
+    bu += lp * (3.0f + auo) + lm * (3.0f - auo);
+    bv += lp * (3.0f + avo) + lm * (3.0f - avo);
+    if (pair_cx(k)) { au[0] += pair_cx(k) * qu; av[0] += pair_cx(k) * qv; }
+    if (pair_cy(k)) { au[1] += pair_cy(k) * qu; av[1] += pair_cy(k) * qv; }
+    if (pair_cz(k)) { au[2] += pair_cz(k) * qu; av[2] += pair_cz(k) * qv; }
+    le += lp * pup + lm * pum;
   }
-  const float ubu = ubar[0] * u[0] + ubar[1] * u[1] + ubar[2] * u[2];
-  mo[0] = rbar[0] - ubu * L.rinv;
-  mo[1] = rbar[1] - ubu * L.rinv;
-  mo[2] = ubar[0] * L.rinv;
-  mo[3] = ubar[1] * L.rinv;
-  mo[4] = ubar[2] * L.rinv;
+  // dL/dtau_a = sum_i lam_i (f_i - E_i(rho^a, u)) / tau_a^2
+  const float dt = dot - r * le;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    sb[a] = ph.g_ba * gbar[1][a];
-    sb[3 + a] = ph.g_ab * gbar[0][a];
+    A.gbar[s][a] = r * (av[a] - v[a] * bv);
+    A.ubar[a] += r * (om1 * (au[a] - u[a] * bu) + (av[a] - v[a] * bv));
   }
-  acc[0] += static_cast<double>(gbar[0][0] * L.S[1][0] + gbar[0][1] * L.S[1][1] + gbar[0][2] * L.S[1][2]) +
-            static_cast<double>(gbar[1][0] * L.S[0][0] + gbar[1][1] * L.S[0][1] + gbar[1][2] * L.S[0][2]);
-  acc[1] += dtau[0];
-  acc[2] += dtau[1];
+  A.rbar[s] = rb;
+  A.dtau[s] = om * om * dt;
+}
+
+// Cell outputs once both species are in: mo = (a^A, a^B, b), sb = Sbar, and
+// the parameter sums.
+__device__ __forceinline__ void adjoint_finish(const AdjointSums& A, const Local& L, const Phys& ph, float mo[5],
+                                               float sb[6], double acc[3]) {
+  const float* u = L.u;
+  const float ubu = A.ubar[0] * u[0] + A.ubar[1] * u[1] + A.ubar[2] * u[2];
+  mo[0] = A.rbar[0] - ubu * L.rinv;
+  mo[1] = A.rbar[1] - ubu * L.rinv;
+  mo[2] = A.ubar[0] * L.rinv;
+  mo[3] = A.ubar[1] * L.rinv;
+  mo[4] = A.ubar[2] * L.rinv;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    sb[a] = ph.g_ba * A.gbar[1][a];
+    sb[3 + a] = ph.g_ab * A.gbar[0][a];
+  }
+  acc[0] += static_cast<double>(A.gbar[0][0] * L.S[1][0] + A.gbar[0][1] * L.S[1][1] + A.gbar[0][2] * L.S[1][2]) +
+            static_cast<double>(A.gbar[1][0] * L.S[0][0] + A.gbar[1][1] * L.S[0][1] + A.gbar[1][2] * L.S[0][2]);
+  acc[1] += A.dtau[0];
+  acc[2] += A.dtau[1];
 }
 
 // ---------------------------------------------------------------------------
@@ -530,6 +475,11 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
         ring[slot * PLANE + at] = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
       }
 
+      if constexpr (M == Mode::Adjoint) {
+        // Finish u here: computed after the barrier it would keep all 38
+        // pulled values alive through the adjoint body.
+        asm volatile("" ::"v"(nxt_u[0]), "v"(nxt_u[1]), "v"(nxt_u[2]));
+      }
       if (k >= 1) {
         __syncthreads();
         const int sm1 = slot >= 1 ? slot - 1 : slot + 4;  // (k-1) % 5
@@ -621,14 +571,32 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
                 shan_chen_finish<EX>(ring + slot * PLANE, at, cur_S);
                 Local L;
                 make_local(cur_rho[0], cur_rho[1], cur_u, cur_S, ph, L);
-                float lam[2][Q];
+                // One species at a time: lam^a = dL/dX at the cell, and the
+                // populations of plane z, pulled again (cache hits) rather
+                // than held in registers since they were first read.
                 const __amdgpu_buffer_rsrc_t rl = plane_rsrc<float>(io.lam, zc, g);
+                __amdgpu_buffer_rsrc_t rc[3];
+                rc[0] = plane_rsrc<T>(io.src, wrap(z - 1, g.nz), g);
+                rc[1] = plane_rsrc<T>(io.src, zc, g);
+                rc[2] = rz[1];
+                AdjointSums A;
 #pragma unroll
-                for (int s = 0; s < 2; ++s)
+                for (int c = 0; c < 3; ++c) A.ubar[c] = 0.0f;
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                  float lam[Q], fs[Q];
 #pragma unroll
                   for (int i = 0; i < Q; ++i)
-                    lam[s][i] = buf_load<float>(rl, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
-                adjoint_cell(cur, lam, L, ph, mo, sb, acc);
+                    lam[i] = buf_load<float>(rl, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
+                  pull_species<S, WALLS>(rc, ppb, col, cur_links, ws[s], s, fs);
+                  float dot = lam[0] * fs[0];
+#pragma unroll
+                  for (int i = 1; i < Q; ++i) dot = fmaf(lam[i], fs[i], dot);
+                  adjoint_species(s, dot, lam, L, ph, A);
+                  // keep the next species' loads below this one's arithmetic
+                  __builtin_amdgcn_sched_barrier(0);
+                }
+                adjoint_finish(A, L, ph, mo, sb, acc);
               }
 #pragma unroll
               for (int c = 0; c < 5; ++c) io.m[c * n + cell] = mo[c];
@@ -643,8 +611,10 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
 
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
+        if constexpr (M != Mode::Adjoint) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) cur[s][i] = nxt[s][i];
+          for (int i = 0; i < Q; ++i) cur[s][i] = nxt[s][i];
+        }
         cur_rho[s] = nxt_rho[s];
       }
 #pragma unroll
@@ -742,9 +712,15 @@ Tiling make_tiling(const Grid& g, int tile, int zchunk) {
   if (zchunk <= 0) {
     // One workgroup fills a CU; march 16 to 64 planes, so that the two planes
     // each workgroup re-reads at the ends of its column cost at most 1/8, with
-    // at least about two workgroups per CU (256 CUs) over the launch.
-    long long zc = (static_cast<long long>(g.nz) * txy + 511) / 512;
-    if (zc < 16) zc = 16;
+    // at least about two workgroups per CU (256 CUs) over the launch.  Small
+    // grids go down to 8 planes to keep one workgroup per CU.
+    const long long cols = static_cast<long long>(g.nz) * txy;
+    long long zc = (cols + 511) / 512;
+    if (zc < 16) {
+      zc = cols / 256;
+      if (zc < 8) zc = 8;
+      if (zc > 16) zc = 16;
+    }
     if (zc > 64) zc = 64;
     if (zc > g.nz) zc = g.nz;
     zchunk = static_cast<int>(zc);
@@ -806,10 +782,12 @@ static hipError_t launch_tile(const Grid& g, const Phys& ph, const Tiling& t, co
     if (t.tile != 0) return hipErrorInvalidValue;
     return launch_shape<S, WALLS, M, 64, 8, 3>(g, ph, t, io, st);
   } else {
-    // The adjoint body holds a third set of 38 values (dL/dX at the cell):
-    // the 64x4 shape (7 waves) leaves it enough registers not to spill.
-    if (t.tile != ADJOINT_TILE) return hipErrorInvalidValue;
-    return launch_shape<S, WALLS, M, 64, 4, 3>(g, ph, t, io, st);
+    switch (t.tile) {
+      case 0: return launch_shape<S, WALLS, M, 64, 8, 3>(g, ph, t, io, st);
+      case 2: return launch_shape<S, WALLS, M, 32, 16, 2>(g, ph, t, io, st);
+      case 4: return launch_shape<S, WALLS, M, 64, 4, 3>(g, ph, t, io, st);
+      default: return hipErrorInvalidValue;
+    }
   }
 }
 

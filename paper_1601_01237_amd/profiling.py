@@ -1,36 +1,227 @@
-"""Plain device-to-device copy for calibrating rocprofv3 byte counters.
+"""Counter runs and their summaries for the fused step (rocprofv3 helpers).
 
-``python -m paper_1601_01237_amd.profiling --gib 2 --reps 3`` runs the
-library's reference streaming copy (lbm_stream_copy) on a buffer of known
-size; the counters of those dispatches divided by the known bytes give the
-scale between the counters and the bytes actually moved on this device.
+Three subcommands:
+
+``run``
+    The program profiled: the library's reference streaming copy
+    (``lbm_stream_copy``) on a buffer of known size, then ``--steps`` fused steps
+    of one workload.  Each step is one launch of the step kernel.
+
+``traffic``
+    Reads the ``counter_collection.csv`` of two ``rocprofv3 --pmc`` runs of
+    ``run`` (one with FETCH_SIZE, one with WRITE_SIZE; both in KiB per
+    dispatch).  The copy moves a known number of bytes each way, so the ratio
+    of that to what the counter reads for it is the counter's scale on this
+    device; the step kernel's counters times that scale are its HBM bytes
+    per launch.  Writes a text summary and an entry of ``profiles/traffic.json``
+    tied to a hash of the kernel sources.
+
+``stats``
+    Formats the ``kernel_stats.csv`` of a ``rocprofv3 --kernel-trace --stats``
+    run as a short text table.
+
+    python -m paper_1601_01237_amd.profiling run --workload 128 --storage fp32
+    python -m paper_1601_01237_amd.profiling traffic --fetch F.csv --write W.csv ...
+    python -m paper_1601_01237_amd.profiling stats --csv kernel_stats.csv ...
 """
 
+from __future__ import annotations
+
 import argparse
+import csv
 import ctypes
+import hashlib
+import json
+import os
+import sys
 
-import torch
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+KERNEL_SOURCES = ("march.hip", "buffer.h", "lattice.h", "launch.h")
+BYTES_PER_CELL = {"fp32": 304, "fp16": 152, "bf16": 152}
+SHAPES = {"128": (128, 128, 128), "512": (512, 512, 512), "walls": (192, 192, 384)}
 
-from . import _lib
+
+def kernel_source_hash():
+    """Hash of the sources the step kernel is built from."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gib", type=float, default=2.0)
-    ap.add_argument("--reps", type=int, default=3)
-    args = ap.parse_args()
+def workload(name, storage):
+    """(shape, kwargs of Sim) of a named benchmark workload."""
+    from . import inputs
+    if name == "128":
+        shape = (128, 128, 128)
+        return shape, dict(rho0=inputs.sphere_droplet(shape, radius=16.0, seed=0), tau=(1.0, 1.0), G=-1.0,
+                           storage=storage)
+    if name == "512":
+        shape = (512, 512, 512)
+        rho0, _, _ = inputs.random_droplets(shape, count=64, rmin=8.0, rmax=24.0, seed=0)
+        return shape, dict(rho0=rho0, tau=(0.6, 0.6), G=-1.0, storage=storage)
+    if name == "walls":
+        shape = (192, 192, 384)
+        rho0, solid = inputs.inclined_channel(shape, angle_deg=30.0, radius=32.0, seed=0)
+        return shape, dict(rho0=rho0, solid=solid, tau=(0.7, 0.7), G=-1.0, storage=storage)
+    raise ValueError(name)
+
+
+def copy_bytes(gib):
+    return (int(gib * (1 << 30)) // 16) * 16
+
+
+def cmd_run(args):
+    import torch
+    from . import _lib
+    from .sim import Sim
     lib = _lib.load()
-    n = (int(args.gib * (1 << 30)) // 16) * 16
+    n = copy_bytes(args.copy_gib)
     src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
     h = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
-    for _ in range(args.reps):
+    for _ in range(args.copy_reps):
         _lib.check("lbm_stream_copy", lib.lbm_stream_copy(ctypes.c_void_p(src.data_ptr()),
                                                            ctypes.c_void_p(dst.data_ptr()), n, h))
     torch.cuda.synchronize()
-    print(f"copied {args.reps} x {n} bytes", flush=True)
+    del src, dst
+    print(f"[profiling] copied {args.copy_reps} x {n} bytes", flush=True)
+    shape, kw = workload(args.workload, args.storage)
+    sim = Sim(**kw)
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    sim.close()
+    print(f"[profiling] {args.workload} {args.storage}: {args.steps} steps of {shape}", flush=True)
+
+
+def _rows(path, counter):
+    with open(path, newline="") as f:
+        return [r for r in csv.DictReader(f) if r["Counter_Name"] == counter]
+
+
+def _mean_kib(rows, pick):
+    vals = [float(r["Counter_Value"]) for r in rows if pick(r["Kernel_Name"])]
+    if not vals:
+        raise SystemExit("no dispatch matched")
+    return sum(vals) / len(vals), len(vals)
+
+
+def _is_copy(name):
+    return "stream_copy_kernel" in name
+
+
+def _is_step(name):
+    return "march_kernel" in name and "(lbm::Mode)0" in name
+
+
+def cmd_traffic(args):
+    known = copy_bytes(args.copy_gib)
+    fetch, write = _rows(args.fetch, "FETCH_SIZE"), _rows(args.write, "WRITE_SIZE")
+    c_rd, n_c = _mean_kib(fetch, _is_copy)
+    c_wr, _ = _mean_kib(write, _is_copy)
+    s_rd, n_s = _mean_kib(fetch, _is_step)
+    s_wr, _ = _mean_kib(write, _is_step)
+    f_rd = known / (c_rd * 1024.0)
+    f_wr = known / (c_wr * 1024.0)
+    rd = s_rd * 1024.0 * f_rd
+    wr = s_wr * 1024.0 * f_wr
+    shape = SHAPES[args.workload]
+    cells = shape[0] * shape[1] * shape[2]
+    algo = BYTES_PER_CELL[args.storage] * cells
+    entry = {
+        "kernel_hash": kernel_source_hash(),
+        "bytes_per_launch": round(rd + wr),
+        "read_bytes_per_launch": round(rd),
+        "write_bytes_per_launch": round(wr),
+        "algorithmic_bytes_per_launch": algo,
+        "traffic_over_algorithmic": round((rd + wr) / algo, 4),
+        "fetch_scale": round(f_rd, 4),
+        "write_scale": round(f_wr, 4),
+        "step_dispatches": n_s,
+        "copy_dispatches": n_c,
+        "command": args.command,
+    }
+    key = f"{args.workload_key}:{args.storage}"
+    rec = {}
+    if os.path.exists(args.json):
+        with open(args.json) as f:
+            rec = json.load(f)
+    rec[key] = entry
+    with open(args.json, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+        f.write("\n")
+    lines = [
+        f"HBM traffic of the fused step, {args.workload_key} {args.storage} ({cells} cells)",
+        "",
+        f"command: {args.command}",
+        "",
+        f"calibration (lbm_stream_copy, {known} bytes read and written per dispatch, {n_c} dispatches):",
+        f"  FETCH_SIZE  {c_rd:14.1f} KiB/dispatch -> scale {f_rd:.4f}",
+        f"  WRITE_SIZE  {c_wr:14.1f} KiB/dispatch -> scale {f_wr:.4f}",
+        f"step kernel ({n_s} dispatches):",
+        f"  FETCH_SIZE  {s_rd:14.1f} KiB/dispatch -> read  {rd / 1e6:10.2f} MB",
+        f"  WRITE_SIZE  {s_wr:14.1f} KiB/dispatch -> write {wr / 1e6:10.2f} MB",
+        f"  total {(rd + wr) / 1e6:.2f} MB per launch vs algorithmic {algo / 1e6:.2f} MB "
+        f"({(rd + wr) / algo:.3f}x); read {rd / (algo / 2):.3f}x, write {wr / (algo / 2):.3f}x",
+        f"kernel source hash {entry['kernel_hash']}",
+    ]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def cmd_stats(args):
+    with open(args.csv, newline="") as f:
+        rows = list(csv.DictReader(f))
+    lines = [args.title, "", f"command: {args.command}", "",
+             f"{'calls':>7} {'avg us':>10} {'min us':>10} {'max us':>10} {'total %':>8}  kernel"]
+    for r in rows:
+        name = r["Name"]
+        if len(name) > 110:
+            name = name[:107] + "..."
+        lines.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:10.2f} "
+                     f"{float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):8.2f}  {name}")
+    if args.bench and os.path.exists(args.bench):
+        with open(args.bench) as f:
+            tail = [ln for ln in f.read().splitlines() if ln.startswith("{")]
+        if tail:
+            lines += ["", "bench line of the same run:", tail[-1]]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    r = sub.add_parser("run")
+    r.add_argument("--workload", default="128", choices=["128", "512", "walls"])
+    r.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
+    r.add_argument("--steps", type=int, default=5)
+    r.add_argument("--copy-gib", type=float, default=2.0)
+    r.add_argument("--copy-reps", type=int, default=3)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--workload", default="128", choices=["128", "512", "walls"])
+    t.add_argument("--workload-key", default="128^3")
+    t.add_argument("--storage", default="fp32")
+    t.add_argument("--copy-gib", type=float, default=2.0)
+    t.add_argument("--json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    t.add_argument("--out", required=True)
+    t.add_argument("--command", default="")
+    s = sub.add_parser("stats")
+    s.add_argument("--csv", required=True)
+    s.add_argument("--out", required=True)
+    s.add_argument("--title", default="rocprofv3 kernel statistics")
+    s.add_argument("--command", default="")
+    s.add_argument("--bench", default=None)
+    args = ap.parse_args(argv)
+    {"run": cmd_run, "traffic": cmd_traffic, "stats": cmd_stats}[args.cmd](args)
 
 
 if __name__ == "__main__":
-    main()
+    sys.exit(main())

@@ -126,14 +126,17 @@ def test_calibration_gradient_16cube_matches_fp64_oracle(lib):
     e_r = rel_err(r0.grad.cpu().numpy(), drho0_ref)
     say(f"16^3 calibration: L {float(L.detach()):.6e} vs {L_ref:.6e}; dL/dG {float(Gt.grad):.6e} vs {dG_ref:.6e} "
         f"({e_G:.1e}); dL/dtau {float(Tt.grad):.6e} vs {dtau_ref:.6e} ({e_t:.1e}); dL/drho0 {e_r:.1e}")
-    assert abs(float(L) - L_ref) <= 1e-5 * L_ref
+    assert abs(float(L.detach()) - L_ref) <= 1e-5 * L_ref
     assert e_G < 1e-3 and e_t < 1e-3 and e_r < 1e-3, (e_G, e_t, e_r)
 
 
 def test_calibration_gradient_against_central_differences(lib):
     from paper_1601_01237_amd.autograd import LBMFunction
     say("calibration gradient vs central differences 16^3 x 100")
-    n, steps, every, h = 16, 100, 25, 1e-4
+    # The FP32 forward leaves ~1e-7 relative rounding noise in the loss; at
+    # h = 1e-3 that is ~0.3% of the central difference, whose O(h^2)
+    # truncation error stays far below it.
+    n, steps, every, h = 16, 100, 25, 1e-3
     rho0, target = _calibration_inputs(n)
     tgt = torch.tensor(target, dtype=torch.float64, device="cuda")
 
@@ -154,7 +157,6 @@ def test_calibration_gradient_against_central_differences(lib):
         v = torch.tensor(inputs.uniform_noise(rho0.shape, seed=4), device="cuda")
         fd_r = (float(loss(G, tau, torch.tensor(rho0, device="cuda") + h * v))
                 - float(loss(G, tau, torch.tensor(rho0, device="cuda") - h * v))) / (2 * h)
-    # FP32 forward: central differences carry ~1e-3 relative noise at h = 1e-4
     assert abs(float(Gt.grad) - fd_G) <= 1e-2 * abs(fd_G), (float(Gt.grad), fd_G)
     assert abs(float(Tt.grad) - fd_t) <= 1e-2 * abs(fd_t), (float(Tt.grad), fd_t)
     ad_r = float((r0.grad * v).sum())

@@ -29,7 +29,10 @@ def _fields(sim):
     return rho.cpu().numpy(), uf.cpu().numpy(), diag
 
 
-@pytest.mark.parametrize("storage,tol_emul", [("fp16", 5e-4), ("bf16", 4e-3)])
+# One unit in the last place of the stored deviation, relative to the field's
+# maximum: FP32 arithmetic against FP64 may round a value to the neighbouring
+# 16-bit number, and the rest population inherits the others' roundings.
+@pytest.mark.parametrize("storage,tol_emul", [("fp16", 2.0 ** -10), ("bf16", 2.0 ** -7)])
 def test_16bit_storage_against_emulated_and_exact_oracle(lib, storage, tol_emul):
     from paper_1601_01237_amd.sim import Sim
     say(f"{storage} 32^3 x 20")
