@@ -114,7 +114,7 @@ def adjoint_cost(n=96, steps=20, adjoint_tile=None):
                 ratio_with_recompute=round((adj_ms + fwd_ms) / fwd_ms, 3))
 
 
-def copy_ceiling(gib=2.0, reps=10):
+def copy_ceiling(gib=4.0, reps=10):
     """Read + write bandwidth of the library's plain streaming copy (GB/s)."""
     import ctypes
     import torch

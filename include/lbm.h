@@ -28,8 +28,14 @@
  *             the current state lives in buf_a if t is even, buf_b if odd.
  *             Stored states and adjoint arrays use the plane-major layout
  *             X[z][a][i][y][x]: element (a, i, x, y, z) at index
- *             ((z*2 + a)*19 + i)*nx*ny + y*nx + x, so that one z plane of all
- *             38 populations is one contiguous block.
+ *             ((z*2 + a)*19 + i)*S + y*nx + x with the plane stride
+ *             S = lbm_plane_stride(nx, ny, storage) >= nx*ny, so that one z
+ *             plane of all 38 populations is one contiguous block.  The S -
+ *             nx*ny elements after each plane are padding (never read):
+ *             population planes a large power of two apart would map the rows
+ *             a step reads together onto the same DRAM channels.  A state (or
+ *             adjoint) buffer holds lbm_state_elems(nx, ny, nz, storage)
+ *             elements.
  *             The pre-collision populations of Eq. (1) at time t are the pull
  *             f_i(x) = X_i(x - c_i), or X_opp(i)(x) if x - c_i is solid.
  *   Memory:   every array pointer is DEVICE memory owned by the caller unless
@@ -126,9 +132,22 @@ lbm_status lbm_velocity_set(int32_t *c, double *w);
 /* Human-readable name of a status code (static string). */
 const char *lbm_status_str(lbm_status s);
 
+/* Elements from one population plane of a stored state to the next (the
+ * plane-major layout above) for storage `storage` (lbm_storage): nx*ny
+ * elements rounded up to 256 bytes, plus 256 bytes when that is a multiple
+ * of 64 KiB.  Adjoint arrays use the FP32 value.  Returns -1 for sizes the
+ * library does not support.  Pure host call. */
+int64_t lbm_plane_stride(int32_t nx, int32_t ny, int32_t storage);
+
+/* Elements of one state buffer (buf_a, buf_b, x_t) of storage `storage`, and
+ * of one adjoint array (lam) with storage LBM_FP32: 2*19*nz*plane stride.
+ * Returns -1 for unsupported sizes.  Pure host call. */
+int64_t lbm_state_elems(int32_t nx, int32_t ny, int32_t nz, int32_t storage);
+
 /* Creates a context and writes the rest state at t = 0 into buf_a.
  *   p      host; copied.
- *   buf_a, buf_b  device, 2*19*N elements of the storage type each.
+ *   buf_a, buf_b  device, lbm_state_elems(nx, ny, nz, storage) elements of
+ *          the storage type each (the padding between planes is not written).
  *   solid  device, N bytes, nonzero = wall cell; NULL = no walls.
  *   rho0   device, 2*N doubles: rho0^a(c) at index a*N + c.  The initial
  *          pre-collision state is f_i^a = w_i rho0^a (Eq. 3 at u = 0) on fluid
@@ -173,22 +192,22 @@ lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
  * planes each workgroup marches through (>= 1; 0 picks a default from the
  * grid).  Shapes (cells in x by y): 0 = 64x8, 1 = 64x12, 2 = 32x16,
  * 3 = 128x4, 4 = 64x4, 5 = 256x2; -1 (the default) picks, among 128x4, 64x8
- * and 32x16 (64x8 and 32x16 with walls), the one that pads the x-y plane
- * least, the wider on a tie.  Results do not depend on this choice (bitwise).
+ * and 32x16 (64x8 and 32x16 with walls or 16-bit storage), the one that pads
+ * the x-y plane least, the first listed on a tie.  Results do not depend on this choice (bitwise).
  * The adjoint march uses the same setting when it is 0, 2 or 4, else the
  * automatic choice with walls; diagnostics use 64x8.  Host-side setting. */
 lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t tile, int32_t zchunk);
 
 /* ---- Adjoint (reverse mode) of one step, FP32 storage only ------------
  * Let X_t be the stored state at t and L a scalar objective.  With
- * lam_{t+1} = dL/dX_{t+1} (device float, 2*19*N, in the plane-major layout of
- * the stored state, see below) this computes
+ * lam_{t+1} = dL/dX_{t+1} (device float, lbm_state_elems(nx, ny, nz,
+ * LBM_FP32), in the plane-major layout of the stored state) this computes
  * lam_t = dL/dX_t, the transpose of one step at X_t (collision with the
  * Eq. 7 gather, then pull streaming with bounce-back).  It also ADDS to
  * dparams (device double[3]): dL/dG (for tied G^{AB} = G^{BA}), dL/dtau_A,
  * dL/dtau_B.  If drho0 (device double, 2*N) is not NULL it receives
  * sum_i w_i dL/df_i^a(x, t): at t = 0 this is dL/drho0 of lbm_init.
- *   x_t    device, 2*19*N of the storage type: X_t (may be a saved copy).
+ *   x_t    device, a state buffer: X_t (may be a saved copy).
  *   work   device scratch; work_bytes must be at least
  *          lbm_adjoint_work_bytes(ctx) for the current tiling (else
  *          LBM_EINVAL).
@@ -200,7 +219,8 @@ lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *x_t, const float *lam_in,
 
 /* dL/dX_T for an objective of the densities at time T: given
  * grad_rho (device float, 2*N, index a*N + c) = dL/drho^a(x, T), writes lam
- * (device float, 2*19*N, plane-major) = dL/dX_T.  Solid cells get zero. */
+ * (device float, an adjoint array, plane-major) = dL/dX_T.  Solid cells get
+ * zero. */
 lbm_status lbm_adjoint_seed(lbm_ctx *ctx, const float *grad_rho, float *lam);
 
 /* Plain device-to-device copy of `bytes` bytes (a multiple of 16; both

@@ -23,16 +23,14 @@ from . import _lib
 from .sim import Sim, _ptr
 
 
-def to_plane_major(f, shape):
-    """(2, 19, nz, ny, nx) populations -> flat plane-major (z, a, i, y, x) layout."""
-    nz, ny, nx = shape
-    return f.reshape(2, _lib.Q, nz, ny, nx).permute(2, 0, 1, 3, 4).contiguous().view(-1)
+def to_plane_major(f, sim):
+    """(2, 19, nz, ny, nx) FP32 array -> adjoint array in the plane-major layout of ``sim``."""
+    return sim.to_state_layout(f, sim.lam_pstride, sim.lam_elems)
 
 
-def from_plane_major(x, shape):
-    """Flat plane-major (z, a, i, y, x) array -> (2, 19, nz, ny, nx)."""
-    nz, ny, nx = shape
-    return x.view(nz, 2, _lib.Q, ny, nx).permute(1, 2, 0, 3, 4).contiguous()
+def from_plane_major(x, sim):
+    """Adjoint array (plane-major layout of ``sim``) -> (2, 19, nz, ny, nx)."""
+    return sim.from_state_layout(x, sim.lam_pstride)
 
 
 class Reverse:
@@ -50,7 +48,7 @@ class Reverse:
     def seed(self, grad_rho):
         """dL/dX_T from dL/drho(T) ((2, nz, ny, nx), any float dtype)."""
         g = grad_rho.to(device=self.sim.device, dtype=torch.float32).contiguous()
-        lam = torch.empty(2 * _lib.Q * self.sim.n, dtype=torch.float32, device=self.sim.device)
+        lam = torch.zeros(self.sim.lam_elems, dtype=torch.float32, device=self.sim.device)
         _lib.check("lbm_adjoint_seed", self.lib.lbm_adjoint_seed(self.sim.ctx, _ptr(g), _ptr(lam)))
         return lam
 

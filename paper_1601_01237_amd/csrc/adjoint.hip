@@ -51,7 +51,7 @@ __device__ __forceinline__ uint64_t near(const Cell3& c, int dx, int dy, int dz,
 // Plane-major index of population (s, i) at (x + dx, y + dy, z + dz).
 __device__ __forceinline__ uint64_t near_pm(const Cell3& c, int s, int i, int dx, int dy, int dz, const Grid& g) {
   const uint64_t x = pick(dx, c.xm, c.x, c.xp), y = pick(dy, c.ym, c.y, c.yp), z = pick(dz, c.zm, c.z, c.zp);
-  return ((z * 2 + s) * Q + i) * g.nxy + y * g.nx + x;
+  return ((z * 2 + s) * Q + i) * g.pstride + y * g.nx + x;
 }
 
 // Adjoint, pass 2: A^b(x) = a^b(x) + sum_i w_i c_i . Sbar^b(x - c_i) on fluid x.
@@ -173,7 +173,7 @@ adjoint_stream_kernel(const Grid g, const Phys ph, const Tiling tl, const uint32
   const uint32_t col_b = col.y[1] + col.x[1];
   const uint32_t col_off = col_b / 4u;
   const int at = (ty + 1) * EX + tx + 1;
-  const uint32_t ppb = g.nxy * 4u;
+  const uint32_t ppb = g.pstride * 4u;
   const float keep[2] = {1.0f - ph.omega[0], 1.0f - ph.omega[1]};
 
   // lam_{t+1} as read by plane p: population i of cell y comes from y + c_i,

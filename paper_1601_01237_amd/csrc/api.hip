@@ -35,12 +35,12 @@ lbm_status from_hip(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; 
 // Step kernel: the selected tile shape (automatic: 128x4 without walls, 64x8
 // with walls, the faster of the shapes measured on each); diagnostics: shape 0.
 Tiling step_tiling(const lbm_ctx* c) {
-  const int tile = c->tile >= 0 ? c->tile : auto_tile(c->g, c->links != nullptr);
+  const int tile = c->tile >= 0 ? c->tile : auto_tile(c->g, c->links != nullptr, static_cast<int>(elem_size(c->storage)));
   return make_tiling(c->g, tile, c->zchunk);
 }
 Tiling aux_tiling(const lbm_ctx* c) { return make_tiling(c->g, 0, 0); }
 Tiling adjoint_tiling(const lbm_ctx* c) {
-  const int tile = adjoint_shape(c->tile) ? c->tile : auto_tile(c->g, true);
+  const int tile = adjoint_shape(c->tile) ? c->tile : auto_tile(c->g, true, 4);
   return make_tiling(c->g, tile, c->tile == tile ? c->zchunk : 0);
 }
 
@@ -91,6 +91,19 @@ const char* lbm_status_str(lbm_status s) {
   return "unknown status";
 }
 
+int64_t lbm_plane_stride(int32_t nx, int32_t ny, int32_t storage) {
+  if (nx < 1 || ny < 1 || storage < LBM_FP32 || storage > LBM_BF16) return -1;
+  const size_t es = elem_size(static_cast<Storage>(storage));
+  if (static_cast<uint64_t>(nx) * ny * es >= (1ull << 31)) return -1;
+  return plane_stride(nx, ny, static_cast<int>(es));
+}
+
+int64_t lbm_state_elems(int32_t nx, int32_t ny, int32_t nz, int32_t storage) {
+  const int64_t s = lbm_plane_stride(nx, ny, storage);
+  if (s < 0 || nz < 1) return -1;
+  return static_cast<int64_t>(2 * LBM_Q) * nz * s;
+}
+
 lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, const uint8_t* solid,
                     const double* rho0, void* stream) {
   if (!out) return LBM_EINVAL;
@@ -108,13 +121,16 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
   const uint64_t nxy = static_cast<uint64_t>(p->nx) * p->ny;
   const uint64_t n = nxy * p->nz;
   const Storage st = static_cast<Storage>(p->storage);
-  // Within one population array, offsets are 32-bit.
+  // Within one population array, offsets are 32-bit; one z plane of all 38
+  // populations is addressed by a single buffer resource.
   if (n * elem_size(st) >= (1ull << 32) || n >= (1ull << 31)) return LBM_ENOTSUP;
+  const uint32_t pstride = plane_stride(p->nx, p->ny, static_cast<int>(elem_size(st)));
+  if (static_cast<uint64_t>(2 * LBM_Q) * pstride * elem_size(st) >= (1ull << 31)) return LBM_ENOTSUP;
 
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) return LBM_EHIP;
   c->p = *p;
-  c->g = Grid{p->nx, p->ny, p->nz, static_cast<uint32_t>(nxy), n};
+  c->g = Grid{p->nx, p->ny, p->nz, static_cast<uint32_t>(nxy), n, pstride};
   for (int a = 0; a < 2; ++a) {
     c->ph.omega[a] = static_cast<float>(1.0 / p->tau[a]);
     c->ph.rho_wall[a] = static_cast<float>(p->rho_wall[a]);

@@ -37,10 +37,10 @@ __device__ __forceinline__ uint64_t shifted(const Coord& p, int dx, int dy, int 
 }
 
 // Plane-major index of population (s, i) at cell (x, y, z) + (dx, dy, dz):
-// X[z][s][i][y][x], i.e. ((z * 2 + s) * 19 + i) * nx * ny + y * nx + x.
+// X[z][s][i][y][x], i.e. ((z * 2 + s) * 19 + i) * pstride + y * nx + x.
 __device__ __forceinline__ uint64_t pm_at(int s, int i, const Coord& p, int dx, int dy, int dz, const Grid& g) {
   const uint64_t x = wrap_u(p.x + dx, g.nx), y = wrap_u(p.y + dy, g.ny), z = wrap_u(p.z + dz, g.nz);
-  return ((z * 2 + s) * Q + i) * g.nxy + y * g.nx + x;
+  return ((z * 2 + s) * Q + i) * g.pstride + y * g.nx + x;
 }
 
 // Canonical SoA index (s * 19 + i) * N + c of the FP32 population interface.
@@ -167,23 +167,15 @@ __global__ void finalize_kernel(const double* __restrict__ partials, int blocks,
 }
 
 // Plain streaming copy: the reference for how much read + write bandwidth
-// the memory system delivers to a kernel.  Each lane keeps four independent
-// 16-byte loads in flight per iteration of a grid-stride loop.
-__global__ void __launch_bounds__(256) stream_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+// the memory system delivers to a kernel.  One 16-byte element per lane and
+// no loop (many short-lived waves keep the most requests in flight), with
+// non-temporal stores.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) stream_copy_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
                                                           uint64_t n16) {
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-  uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
-  for (; i + 3 * stride < n16; i += 4 * stride) {
-    const uint4 a = src[i];
-    const uint4 b = src[i + stride];
-    const uint4 c = src[i + 2 * stride];
-    const uint4 d = src[i + 3 * stride];
-    dst[i] = a;
-    dst[i + stride] = b;
-    dst[i + 2 * stride] = c;
-    dst[i + 3 * stride] = d;
-  }
-  for (; i < n16; i += stride) dst[i] = src[i];
+  const uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  if (i < n16) __builtin_nontemporal_store(src[i], &dst[i]);
 }
 
 unsigned grid_for(uint64_t n) {
@@ -194,6 +186,13 @@ unsigned grid_for(uint64_t n) {
 }
 
 }  // namespace
+
+uint32_t plane_stride(int nx, int ny, int elem_bytes) {
+  const uint64_t bytes = static_cast<uint64_t>(nx) * ny * elem_bytes;
+  uint64_t padded = ((bytes + 255) / 256) * 256;
+  if (padded % 65536 == 0) padded += 256;
+  return static_cast<uint32_t>(padded / elem_bytes);
+}
 
 hipError_t launch_links(const Grid& g, const uint8_t* solid, uint32_t* links, hipStream_t st) {
   hipLaunchKernelGGL(links_kernel, dim3(grid_for(g.n)), dim3(TPB), 0, st, g, solid, links);
@@ -265,11 +264,11 @@ hipError_t launch_finalize(const double* partials, int blocks, int nvals, const 
 
 hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStream_t st) {
   const uint64_t n16 = bytes / 16;
-  uint64_t blocks = (n16 + TPB - 1) / TPB;
-  if (blocks > 256ull * 8) blocks = 256ull * 8;  // 8 workgroups per CU, grid-stride beyond that
-  if (blocks == 0) blocks = 1;
+  if (n16 == 0) return hipSuccess;
+  const uint64_t blocks = (n16 + TPB - 1) / TPB;
+  if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
   hipLaunchKernelGGL(stream_copy_kernel, dim3(static_cast<unsigned>(blocks)), dim3(TPB), 0, st,
-                     static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+                     static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), n16);
   return hipGetLastError();
 }
 

@@ -44,13 +44,14 @@ __device__ __forceinline__ Column make_column(int ex, int ey, const Grid& g) {
 }
 
 // Buffer resource over the 38 population planes of z plane `zw`
-// (plane-major layout X[z][a][i][y][x]).  Out-of-range offsets read as zero
+// (plane-major layout X[z][a][i][y][x], population planes g.pstride elements
+// apart).  Out-of-range offsets read as zero
 // instead of faulting.
 constexpr int RSRC_FLAGS = 0x00020000;  // 32-bit data format, gfx9 family
 
 template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* buf, int zw, const Grid& g) {
-  const uint64_t block = static_cast<uint64_t>(2 * Q) * g.nxy * sizeof(T);
+  const uint64_t block = static_cast<uint64_t>(2 * Q) * g.pstride * sizeof(T);
   const char* base = static_cast<const char*>(buf) + static_cast<uint64_t>(zw) * block;
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), static_cast<short>(0),
                                            static_cast<int>(block), RSRC_FLAGS);

@@ -11,9 +11,17 @@ namespace lbm {
 // Per-launch description of the grid and the physics, shared by every kernel.
 struct Grid {
   int nx, ny, nz;
-  uint32_t nxy;  // nx * ny
-  uint64_t n;    // nx * ny * nz
+  uint32_t nxy;      // nx * ny
+  uint64_t n;        // nx * ny * nz
+  uint32_t pstride;  // elements from one population plane to the next (>= nxy, padded)
 };
+
+// Elements per population plane of the stored state for a storage element
+// size: the plane rounded up to 256 bytes, plus 256 bytes when that is a
+// multiple of 64 KiB.  Planes a large power of two apart put the rows a step
+// reads together on the same DRAM channels (measured: 4-5% of step time at
+// 128^2 and 512^2 planes); other plane sizes are left unpadded.
+uint32_t plane_stride(int nx, int ny, int elem_bytes);
 
 struct Phys {
   float omega[2];     // 1 / tau_a
@@ -35,7 +43,7 @@ constexpr int TILE_SHAPES = 6;
 constexpr bool adjoint_shape(int tile) { return tile == 0 || tile == 2 || tile == 4; }
 Tiling make_tiling(const Grid& g, int tile, int zchunk);
 // Shape used when the caller asks for the automatic choice.
-int auto_tile(const Grid& g, bool walls);
+int auto_tile(const Grid& g, bool walls, int elem_bytes);
 
 // Diagnostic region (device-side floats).
 struct Region {

@@ -18,7 +18,8 @@
 //
 // Memory layout: plane-major X[z][a][i][y][x], x fastest, so each population
 // load of a 64-wide row is one contiguous 256-byte run (FP32) and one z plane
-// of all 38 populations is one contiguous block.  Blocks are remapped
+// of all 38 populations is one contiguous block; population planes are padded
+// (Grid::pstride) so that they are not a power of two apart.  Blocks are remapped
 // so that the tiles dispatched to one XCD (block id mod 8) are contiguous in
 // x and y and share that XCD's L2 for the halo re-reads.
 
@@ -422,7 +423,7 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
   const int kmax = z1 - z0 + 1;  // planes p_k = z0 - 1 + k for k = 0..kmax
 
   const uint64_t n = g.n;
-  const uint32_t ppb = g.nxy * static_cast<uint32_t>(sizeof(T));  // bytes of one population plane
+  const uint32_t ppb = g.pstride * static_cast<uint32_t>(sizeof(T));  // bytes between population planes
 
   float ws[2][3];
 #pragma unroll
@@ -733,14 +734,17 @@ Tiling make_tiling(const Grid& g, int tile, int zchunk) {
   return t;
 }
 
-int auto_tile(const Grid& g, bool walls) {
-  // Widest rows first: 128-lane rows read whole 512-byte population rows.
-  // A shape wins only by padding the x-y plane less (lanes past nx or ny do no
-  // work).  The (128, 4) shape keeps too few registers for the wall path.
+int auto_tile(const Grid& g, bool walls, int elem_bytes) {
+  // FP32 without walls: widest rows first (128-lane rows read whole 512-byte
+  // population rows).  With walls (the 128 x 4 shape keeps too few registers
+  // for the wall path) and for 16-bit storage (measured faster) 64 x 8 comes
+  // first.  A later shape wins only by padding the x-y plane less (lanes past
+  // nx or ny do no work).
   static constexpr int open_order[] = {3, 0, 2};
-  static constexpr int wall_order[] = {0, 2};
-  const int* order = walls ? wall_order : open_order;
-  const int count = walls ? 2 : 3;
+  static constexpr int tall_order[] = {0, 2};
+  const bool tall = walls || elem_bytes != 4;
+  const int* order = tall ? tall_order : open_order;
+  const int count = tall ? 2 : 3;
   int best = order[0];
   long long best_cells = -1;
   for (int k = 0; k < count; ++k) {

@@ -80,9 +80,18 @@ class Sim:
         p.rho_wall[0], p.rho_wall[1] = self.rho_wall
         self.params = p
 
+        # Plane-major state layout with padded population planes (lbm.h).
+        self.pstride = int(self.lib.lbm_plane_stride(nx, ny, code))
+        self.state_elems = int(self.lib.lbm_state_elems(nx, ny, nz, code))
+        self.lam_pstride = int(self.lib.lbm_plane_stride(nx, ny, _lib.FP32))
+        self.lam_elems = int(self.lib.lbm_state_elems(nx, ny, nz, _lib.FP32))
+        if min(self.pstride, self.state_elems, self.lam_elems) < 0:
+            raise ValueError(f"grid {self.shape} is not supported")
+
         with torch.cuda.device(self.device):
             self.stream = torch.cuda.current_stream(self.device)
-            self.bufs = [torch.empty(2 * Q * self.n, dtype=self.dtype, device=self.device) for _ in range(2)]
+            # zeroed so that the padding between planes holds defined values
+            self.bufs = [torch.zeros(self.state_elems, dtype=self.dtype, device=self.device) for _ in range(2)]
             self.rho0_dev = rho0.to(self.device).contiguous()
             self.solid_dev = None
             if solid is not None:
@@ -126,6 +135,25 @@ class Sim:
     def state(self):
         """The stored (post-collision) buffer of the current time level."""
         return self.bufs[self.t & 1]
+
+    def plane_view(self, flat, pstride=None):
+        """(nz, 2, 19, ny, nx) view of a flat plane-major buffer (state layout)."""
+        nz, ny, nx = self.shape
+        ps = self.pstride if pstride is None else pstride
+        return flat.view(nz, 2, Q, ps)[..., : nx * ny].unflatten(-1, (ny, nx))
+
+    def to_state_layout(self, f, pstride=None, elems=None):
+        """(2, 19, nz, ny, nx) array -> new flat plane-major buffer (zero padding)."""
+        nz, ny, nx = self.shape
+        ps = self.pstride if pstride is None else pstride
+        n = self.state_elems if elems is None else elems
+        out = torch.zeros(n, dtype=f.dtype, device=f.device)
+        self.plane_view(out, ps).copy_(f.reshape(2, Q, nz, ny, nx).permute(2, 0, 1, 3, 4))
+        return out
+
+    def from_state_layout(self, flat, pstride=None):
+        """Flat plane-major buffer -> (2, 19, nz, ny, nx) contiguous copy."""
+        return self.plane_view(flat, pstride).permute(1, 2, 0, 3, 4).contiguous()
 
     # -- observables -------------------------------------------------------------
     def moments(self, region=None, want_fields=True):

@@ -89,3 +89,24 @@ def test_parameter_checks_without_a_gpu(lib):
     # population arrays beyond 32-bit offsets are refused
     p.nx, p.ny, p.nz = 2048, 1024, 1024
     assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), dummy_a, dummy_b, None, dummy_r, None) == -5
+
+
+def test_plane_stride_and_state_size(lib):
+    """Padded plane-major layout: each population plane rounded up to 256 bytes,
+    plus 256 bytes when that is a multiple of 64 KiB."""
+    from paper_1601_01237_amd import _lib
+    for nx, ny, st, es in [(128, 128, _lib.FP32, 4), (128, 128, _lib.FP16, 2), (96, 96, _lib.FP32, 4),
+                           (70, 19, _lib.BF16, 2), (512, 512, _lib.FP32, 4), (1, 1, _lib.FP32, 4),
+                           (32, 30, _lib.FP32, 4), (384, 192, _lib.FP32, 4), (256, 256, _lib.BF16, 2)]:
+        nbytes = nx * ny * es
+        padded = -(-nbytes // 256) * 256
+        if padded % 65536 == 0:
+            padded += 256
+        want = padded // es
+        got = lib.lbm_plane_stride(nx, ny, st)
+        assert got == want, (nx, ny, st, got, want)
+        assert got >= nx * ny and (got * es) % 65536 != 0
+        assert lib.lbm_state_elems(nx, ny, 7, st) == 2 * 19 * 7 * want
+    assert lib.lbm_plane_stride(0, 4, _lib.FP32) == -1
+    assert lib.lbm_plane_stride(4, 4, 3) == -1
+    assert lib.lbm_state_elems(4, 4, 0, _lib.FP32) == -1

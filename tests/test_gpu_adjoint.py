@@ -53,8 +53,8 @@ def test_one_adjoint_step_matches_oracle(lib, walls):
     lam1 = lam1.astype(np.float32)
     rev = Reverse(sim)
     x_t = sim.state
-    lam_gpu, drho = rev.step(x_t, to_plane_major(torch.from_numpy(lam1).cuda(), shape), want_drho0=True)
-    got = from_plane_major(lam_gpu, shape).cpu().numpy()
+    lam_gpu, drho = rev.step(x_t, to_plane_major(torch.from_numpy(lam1).cuda(), sim), want_drho0=True)
+    got = from_plane_major(lam_gpu, sim).cpu().numpy()
 
     mu, dG, dtau = oadj.collide_adjoint(f, lam1.astype(np.float64), p, solid)
     want = oadj.stream_adjoint(mu, solid)
@@ -91,7 +91,7 @@ def test_seed_matches_oracle(lib):
     g = np.random.default_rng(3).normal(size=(2,) + shape)
     g[:, solid] = 0.0
     lam = Reverse(sim).seed(torch.from_numpy(g))
-    got = from_plane_major(lam, shape).cpu().numpy()
+    got = from_plane_major(lam, sim).cpu().numpy()
     lam_f = np.repeat(g[:, None], 19, axis=1)
     want = oadj.stream_adjoint(lam_f, solid)
     assert rel_err(got, want) < 1e-6

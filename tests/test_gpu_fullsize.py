@@ -51,12 +51,12 @@ def _decode(raw, storage, shift):
     return x
 
 
-def _patches(state, shape, centers):
+def _patches(sim, centers):
     """Stored values of the 5^3 periodic patches around ``centers`` -> (S, 5, 5, 5, 2, 19)."""
-    nz, ny, nx = shape
-    st = state.view(nz, 2, olbm.Q, ny, nx)
-    d = torch.arange(-2, 3, device=state.device)
-    c = torch.as_tensor(centers, device=state.device)
+    nz, ny, nx = sim.shape
+    st = sim.plane_view(sim.state)
+    d = torch.arange(-2, 3, device=st.device)
+    c = torch.as_tensor(centers, device=st.device)
     zi = (c[:, 0, None] + d[None, :]) % nz
     yi = (c[:, 1, None] + d[None, :]) % ny
     xi = (c[:, 2, None] + d[None, :]) % nx
@@ -92,9 +92,9 @@ def _sampled_step(rho0, tau, G, storage, solid=None, label="", warm=3):
     sim = Sim(rho0, tau=(tau, tau), G=G, storage=storage, solid=solid)
     sim.step(warm)
     centers = _centers(shape, solid, seed=7)
-    before = _patches(sim.state, shape, centers)
+    before = _patches(sim, centers)
     sim.step(1)
-    after = _patches(sim.state, shape, centers)[:, 2, 2, 2]
+    after = _patches(sim, centers)[:, 2, 2, 2]
     torch.cuda.synchronize()
     shift = sim.rho_shift
     sim.close()
