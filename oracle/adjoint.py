@@ -75,6 +75,8 @@ def collide_adjoint(f, lam_star, p: Params, solid=None):
     Returns ``(lam, dG, dtau)``: lam = dL/df (same shape as f), dG a (2, 2)
     array of dL/dG^{ab} and dtau a length-2 array of dL/dtau_a.
     """
+    if p.collision != "bgk":
+        raise NotImplementedError("the adjoint is written for the BGK collision of Eq. (2)")
     m = lbm.macroscopic(f, p, solid)
     fluid, rho_s, rho, u = m["fluid"], m["rho_s"], m["rho"], m["u"]
     shape = f.shape[2:]

@@ -13,6 +13,8 @@ benchmark cases required for engineering applications" (arXiv 1601.01237):
 * Eq. (3)  third-order equilibrium, lattice temperature T0 = 1/3;
 * Eqs. (4)-(6) species density, mixture density, mixture velocity;
 * Eq. (7)  Shan-Chen inter-component force, G^{aa} = 0 (Sec. 2);
+* Eqs. (10)-(11) regularized collision of Sec. 3 (second-order Hermite
+  projection of the non-equilibrium part, a reading: see regularized_neq);
 * Eqs. (8)-(9) force velocity u_F = u + g/2 and g = sum_a g^a rho^a / rho,
   with g^a = sum_b F^{ab} / rho^a;
 * Sec. 4 pointwise (halfway) bounce-back wall and the pointwise wall
@@ -74,6 +76,7 @@ class Params:
     tau: tuple = (1.0, 1.0)                     # tau_A, tau_B  (Eq. 2)
     G: tuple = ((0.0, -1.0), (-1.0, 0.0))       # G^{ab}       (Eq. 7), G^{aa} = 0
     rho_wall: tuple = (0.0, 0.0)                # rho_s^a      (Sec. 4)
+    collision: str = "bgk"                      # "bgk" (Eq. 2) or "regularized" (Eqs. 10-11)
     extra: dict = field(default_factory=dict)
 
 
@@ -194,9 +197,41 @@ def macroscopic(f, p: Params, solid=None):
     return dict(fluid=fluid, rho_s=rho_s, rho=rho, u=u, F=F, g=g)
 
 
-def collide(f, p: Params, solid=None):
-    """Right-hand side of Eq. (1): f* = f + C_i^a + F_i^a with BGK (Eq. 2).
+def momentum_flux_neq(f_a, rho_a, u):
+    """Non-equilibrium momentum flux Pi^a = sum_i c_i c_i (f_i^a - f_i^eq(rho^a, u)).
 
+    Returns (3, 3, nz, ny, nx) (symmetric)."""
+    d = f_a - equilibrium(rho_a, u)
+    out = np.empty((3, 3) + rho_a.shape, dtype=d.dtype)
+    for a in range(3):
+        for b in range(3):
+            out[a, b] = np.einsum("i,izyx->zyx", C[:, a] * C[:, b], d)
+    return out
+
+
+def regularized_neq(f_a, rho_a, u):
+    """Regularized non-equilibrium part, Eq. (11): f^neq_i = Phi_i : Pi^a.
+
+    Reading of Phi (the paper delegates it to citations): the second-order
+    Hermite projection Phi_i = w_i (c_i c_i - T0 I) / (2 T0^2), which keeps
+    exactly the non-equilibrium momentum flux (the second moment) and drops
+    every higher-order non-equilibrium moment.  Returns (19, nz, ny, nx).
+    """
+    pi = momentum_flux_neq(f_a, rho_a, u)
+    trace = pi[0, 0] + pi[1, 1] + pi[2, 2]
+    out = np.empty((Q,) + rho_a.shape, dtype=pi.dtype)
+    for i in range(Q):
+        cpc = sum(C[i, a] * C[i, b] * pi[a, b] for a in range(3) for b in range(3))
+        out[i] = W[i] * (cpc - T0 * trace) / (2.0 * T0 * T0)
+    return out
+
+
+def collide(f, p: Params, solid=None):
+    """Right-hand side of Eq. (1): f* = f + C_i^a + F_i^a.
+
+    BGK (Eq. 2): f* = f - (f - f^eq) / tau + F.
+    Regularized (Eqs. 10-11): f* = f^eq + (1 - 1/tau) f^neq + F with the
+    projected f^neq of :func:`regularized_neq`.
     Solid cells keep zero populations.
     """
     m = macroscopic(f, p, solid)
@@ -205,9 +240,15 @@ def collide(f, p: Params, solid=None):
                                                   np.asarray(p.G).dtype))
     for a in range(2):
         feq = equilibrium(rho_s[a], u)
-        coll = -(f[a] - feq) / p.tau[a]
         force = forcing_term(rho_s[a], u, g[a])
-        fstar[a] = np.where(fluid, f[a] + coll + force, 0.0)
+        if p.collision == "bgk":
+            coll = -(f[a] - feq) / p.tau[a]
+            fstar[a] = np.where(fluid, f[a] + coll + force, 0.0)
+        elif p.collision == "regularized":
+            neq = regularized_neq(f[a], rho_s[a], u)
+            fstar[a] = np.where(fluid, feq + (1.0 - 1.0 / p.tau[a]) * neq + force, 0.0)
+        else:
+            raise ValueError(p.collision)
     return fstar
 
 

@@ -34,10 +34,12 @@ def feq(rho, u, c, w):
                       + cu ** 3 / (6 * T0 ** 3) - cu * uu / (2 * T0 * T0))
 
 
-def step(f, shape, tau, G, solid, rho_wall):
+def step(f, shape, tau, G, solid, rho_wall, collision="bgk"):
     """One step.  ``f[s][q][(z, y, x)]`` nested lists/dicts in this module's order.
 
-    ``solid`` is a set of (z, y, x) wall cells.  Returns the new state.
+    ``solid`` is a set of (z, y, x) wall cells.  ``collision`` is "bgk"
+    (Eq. 2) or "regularized" (Eqs. 10-11 with the non-equilibrium part
+    replaced by its second-order Hermite component).  Returns the new state.
     """
     vel, w, opp = lattice()
     nz, ny, nx = shape
@@ -77,11 +79,22 @@ def step(f, shape, tau, G, solid, rho_wall):
             force = [G[s][other] * rho[cell][s] * acc[a] for a in range(3)]
             g = [force[a] / rho[cell][s] for a in range(3)]
             v = [u[a] + g[a] for a in range(3)]
+            e_u = [feq(rho[cell][s], u, vel[q], w[q]) for q in range(19)]
+            e_v = [feq(rho[cell][s], v, vel[q], w[q]) for q in range(19)]
+            if collision == "regularized":
+                # second moment of the non-equilibrium part, then its
+                # Hermite-2 reconstruction w_q (c c - T0 I) : Pi / (2 T0^2)
+                pi = [[sum(vel[q][a] * vel[q][b] * (f[s][q][cell] - e_u[q]) for q in range(19))
+                       for b in range(3)] for a in range(3)]
+                trace = pi[0][0] + pi[1][1] + pi[2][2]
             for q in range(19):
-                e_u = feq(rho[cell][s], u, vel[q], w[q])
-                e_v = feq(rho[cell][s], v, vel[q], w[q])
                 fq = f[s][q][cell]
-                fstar[s][q][cell] = fq - (fq - e_u) / tau[s] + (e_v - e_u)
+                if collision == "regularized":
+                    cpc = sum(vel[q][a] * vel[q][b] * pi[a][b] for a in range(3) for b in range(3))
+                    neq = w[q] * (cpc - T0 * trace) / (2.0 * T0 * T0)
+                    fstar[s][q][cell] = e_u[q] + (1.0 - 1.0 / tau[s]) * neq + (e_v[q] - e_u[q])
+                else:
+                    fstar[s][q][cell] = fq - (fq - e_u[q]) / tau[s] + (e_v[q] - e_u[q])
 
     new = [[dict() for _ in range(19)] for _ in range(2)]
     for cell in cells:
