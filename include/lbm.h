@@ -75,6 +75,17 @@ typedef enum {
  * 16-bit forms store X_i - w_i * rho_shift[a] rounded to nearest even. */
 typedef enum { LBM_FP32 = 0, LBM_FP16 = 1, LBM_BF16 = 2 } lbm_storage;
 
+/* Collision operator.
+ *   LBM_BGK          Eq. (2): f* = f - (f - f^eq)/tau + F.
+ *   LBM_REGULARIZED  Eqs. (10)-(11) of Sec. 3: f* = f^eq + (1 - 1/tau) f^neq
+ *                    + F, where f^neq is the second-order Hermite projection
+ *                    w_i (c_i c_i - T0 I) : Pi / (2 T0^2) of the
+ *                    non-equilibrium part (Pi = sum_i c_i c_i (f_i - f^eq_i))
+ *                    -- a reading: the paper names the filter and takes its
+ *                    formula from citations.
+ * F is the exact-difference forcing term in both. */
+typedef enum { LBM_BGK = 0, LBM_REGULARIZED = 1 } lbm_collision;
+
 #define LBM_Q 19
 #define LBM_DIAG_LEN 16
 
@@ -99,8 +110,7 @@ enum {
 };
 
 typedef struct {
-  int32_t nx, ny, nz;  /* >= 1 each; 2*19*N elements of the storage type     */
-                       /* per buffer; N * element size must stay below 4 GiB */
+  int32_t nx, ny, nz;  /* >= 1 each; N * element size must stay below 4 GiB */
   int32_t storage;     /* lbm_storage                                        */
   double tau[2];       /* relaxation times tau_A, tau_B (Eq. 2), > 1/2       */
   double G[2][2];      /* interaction matrix G^{ab} of Eq. (7), paper sign:  */
@@ -109,6 +119,7 @@ typedef struct {
   double rho_shift[2]; /* shift of the 16-bit storage forms (ignored in FP32)*/
   double rho_wall[2];  /* wall potential rho_s^a (Sec. 4): the density a     */
                        /* solid neighbour contributes to the Eq. (7) sum     */
+  int32_t collision;   /* lbm_collision                                      */
 } lbm_params;
 
 /* Region parameters of the diagnostic vector (host struct). */
@@ -198,7 +209,8 @@ lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
  * automatic choice with walls; diagnostics use 64x8.  Host-side setting. */
 lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t tile, int32_t zchunk);
 
-/* ---- Adjoint (reverse mode) of one step, FP32 storage only ------------
+/* ---- Adjoint (reverse mode) of one step, FP32 storage and BGK only -----
+ * (other storage forms or the regularized collision: LBM_ENOTSUP) 
  * Let X_t be the stored state at t and L a scalar objective.  With
  * lam_{t+1} = dL/dX_{t+1} (device float, lbm_state_elems(nx, ny, nz,
  * LBM_FP32), in the plane-major layout of the stored state) this computes

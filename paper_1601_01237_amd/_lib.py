@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 Q = 19
 DIAG_LEN = 16
 FP32, FP16, BF16 = 0, 1, 2
+BGK, REGULARIZED = 0, 1
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "HIP runtime error", -3: "invalid state",
           -4: "non-finite values (unstable run)", -5: "not supported"}
@@ -35,6 +36,7 @@ class Params(C.Structure):
         ("G", (C.c_double * 2) * 2),
         ("rho_shift", C.c_double * 2),
         ("rho_wall", C.c_double * 2),
+        ("collision", C.c_int32),
     ]
 
 

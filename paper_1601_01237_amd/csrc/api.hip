@@ -118,6 +118,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
       if (!std::isfinite(p->G[a][b])) return LBM_EINVAL;
   }
   if (p->G[0][0] != 0.0 || p->G[1][1] != 0.0) return LBM_ENOTSUP;
+  if (p->collision != LBM_BGK && p->collision != LBM_REGULARIZED) return LBM_EINVAL;
   const uint64_t nxy = static_cast<uint64_t>(p->nx) * p->ny;
   const uint64_t n = nxy * p->nz;
   const Storage st = static_cast<Storage>(p->storage);
@@ -136,6 +137,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
     c->ph.rho_wall[a] = static_cast<float>(p->rho_wall[a]);
     c->ph.shift[a] = st == Storage::F32 ? 0.0f : static_cast<float>(p->rho_shift[a]);
   }
+  c->ph.regularized = p->collision == LBM_REGULARIZED ? 1 : 0;
   c->ph.g_ab = static_cast<float>(p->G[0][1]);
   c->ph.g_ba = static_cast<float>(p->G[1][0]);
   c->storage = st;
@@ -273,7 +275,7 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, fl
   if (work_bytes < lbm_adjoint_work_bytes(c)) return LBM_EINVAL;
   if (lam_in == lam_out || static_cast<const void*>(lam_in) == x_t || static_cast<const void*>(lam_out) == x_t)
     return LBM_EINVAL;
-  if (c->storage != Storage::F32) return LBM_ENOTSUP;
+  if (c->storage != Storage::F32 || c->ph.regularized) return LBM_ENOTSUP;
   const Tiling t = adjoint_tiling(c);
   if (t.blocks <= 0) return LBM_ENOTSUP;
   float* m = static_cast<float*>(work);

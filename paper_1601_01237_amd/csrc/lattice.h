@@ -18,6 +18,7 @@ constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0
 constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
+constexpr float T0F = 1.0f / 3.0f;  // lattice temperature T0 (Sec. 2)
 constexpr float W0 = 1.0f / 3.0f;
 constexpr float WF = 1.0f / 18.0f;
 constexpr float WE = 1.0f / 36.0f;
@@ -43,26 +44,30 @@ template <> struct StorageTraits<Storage::F32> {
   __device__ static inline float encode(float v) { return v; }
 };
 
+// The 16-bit forms store X - w_shift: decode_add reads a stored value back as
+// X, sub_encode rounds X - w_shift to the storage type.  (Mixed-precision
+// FMAs would fuse the FP16 pair into one instruction each, but measured
+// slower on gfx950 than convert plus add.)
 template <> struct StorageTraits<Storage::F16> {
   using T = _Float16;
   static constexpr bool shifted = true;
   __device__ static inline float decode(_Float16 v) { return static_cast<float>(v); }
   __device__ static inline _Float16 encode(float v) { return static_cast<_Float16>(v); }
+  __device__ static inline float decode_add(_Float16 v, float ws) { return decode(v) + ws; }
+  __device__ static inline _Float16 sub_encode(float x, float ws) { return encode(x - ws); }
 };
 
 // bfloat16 kept as its bit pattern: the upper half of an IEEE binary32.
+// Encoding rounds to nearest, ties to even (the native conversion).
 template <> struct StorageTraits<Storage::BF16> {
   using T = uint16_t;
   static constexpr bool shifted = true;
   __device__ static inline float decode(uint16_t v) {
     return __uint_as_float(static_cast<uint32_t>(v) << 16);
   }
-  // Round to nearest, ties to even, on the 16 discarded mantissa bits.
-  __device__ static inline uint16_t encode(float v) {
-    uint32_t b = __float_as_uint(v);
-    b += 0x7FFFu + ((b >> 16) & 1u);
-    return static_cast<uint16_t>(b >> 16);
-  }
+  __device__ static inline uint16_t encode(float v) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v)); }
+  __device__ static inline float decode_add(uint16_t v, float ws) { return decode(v) + ws; }
+  __device__ static inline uint16_t sub_encode(float x, float ws) { return encode(x - ws); }
 };
 
 }  // namespace lbm

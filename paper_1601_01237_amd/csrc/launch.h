@@ -28,6 +28,7 @@ struct Phys {
   float g_ab, g_ba;   // G^{AB}, G^{BA}
   float rho_wall[2];  // rho_s^a
   float shift[2];     // rho_shift^a of the 16-bit storage forms (0 for FP32)
+  int regularized;    // collision operator: 0 = BGK (Eq. 2), 1 = regularized (Eqs. 10-11)
 };
 
 struct Tiling {

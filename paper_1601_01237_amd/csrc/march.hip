@@ -52,9 +52,11 @@ __device__ __forceinline__ void pull_species(const __amdgpu_buffer_rsrc_t rz[3],
     } else {
       v = buf_load<T>(rz[1 - CZ[i]], off, static_cast<uint32_t>(s * Q + i) * ppb);
     }
-    float x = Tr::decode(v);
-    if constexpr (Tr::shifted) x += ws[i == 0 ? 0 : (i <= 6 ? 1 : 2)];
-    f[i] = x;
+    if constexpr (Tr::shifted) {
+      f[i] = Tr::decode_add(v, ws[i == 0 ? 0 : (i <= 6 ? 1 : 2)]);
+    } else {
+      f[i] = Tr::decode(v);
+    }
   }
 }
 
@@ -219,6 +221,61 @@ __device__ __forceinline__ void collide(float f[2][Q], const Local& L, const Phy
 #pragma unroll
     for (int i = 2; i < Q; ++i) moving += f[s][i];
     f[s][0] = r[s] - moving;
+  }
+}
+
+// Regularized collision, Eqs. (10)-(11): f* = E(rho^a, u + g^a) +
+// (1 - w) w_i (c_i c_i - T0 I) : Pi^a / (2 T0^2), the second-order Hermite
+// projection of the non-equilibrium part, with
+// Pi^a = sum_i c_i c_i f_i - rho^a (T0 I + u u) (the second moment of Eq. 3
+// is exactly rho (T0 I + u u) on D3Q19).  The projection is even in c_i, so
+// both members of a pair get the same non-equilibrium part.  The rest
+// population is again the remainder rho^a - sum_{i>0} f*_i.
+__device__ __forceinline__ void collide_regularized(float f[2][Q], const Local& L, const Phys& ph) {
+  const float ux = L.u[0], uy = L.u[1], uz = L.u[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const float r = L.rho[s];
+    float e[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) e[k] = f[s][2 * k + 1] + f[s][2 * k + 2];
+    const float rt = r * T0F;
+    const float pxx = (((e[0] + e[3]) + (e[4] + e[5])) + e[6]) - fmaf(r * ux, ux, rt);
+    const float pyy = (((e[1] + e[3]) + (e[4] + e[7])) + e[8]) - fmaf(r * uy, uy, rt);
+    const float pzz = (((e[2] + e[5]) + (e[6] + e[7])) + e[8]) - fmaf(r * uz, uz, rt);
+    const float pxy = (e[3] - e[4]) - (r * ux) * uy;
+    const float pxz = (e[5] - e[6]) - (r * ux) * uz;
+    const float pyz = (e[7] - e[8]) - (r * uy) * uz;
+    const float tt = T0F * ((pxx + pyy) + pzz);
+    float h[9];  // c . Pi . c - T0 tr(Pi) for pair k
+    h[0] = pxx - tt;
+    h[1] = pyy - tt;
+    h[2] = pzz - tt;
+    h[3] = fmaf(2.0f, pxy, pxx + pyy) - tt;
+    h[4] = fmaf(-2.0f, pxy, pxx + pyy) - tt;
+    h[5] = fmaf(2.0f, pxz, pxx + pzz) - tt;
+    h[6] = fmaf(-2.0f, pxz, pxx + pzz) - tt;
+    h[7] = fmaf(2.0f, pyz, pyy + pzz) - tt;
+    h[8] = fmaf(-2.0f, pyz, pyy + pzz) - tt;
+    const float vx = ux + L.g[s][0], vy = uy + L.g[s][1], vz = uz + L.g[s][2];
+    const float vv = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
+    const float av = fmaf(-1.5f, vv, 1.0f);
+    const float bv = fmaf(-4.5f, vv, 3.0f);
+    const float keep45 = 4.5f * (1.0f - ph.omega[s]);  // (1 - w) / (2 T0^2)
+    float moving = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const float cv = pair_dot(k, vx, vy, vz);
+      const float tv = cv * cv;
+      const float ev = fmaf(4.5f, tv, av);
+      const float ov = cv * fmaf(4.5f, tv, bv);
+      const float w = pair_w(k);
+      const float neq = w * (keep45 * h[k]);
+      f[s][2 * k + 1] = fmaf(w * r, ev + ov, neq);
+      f[s][2 * k + 2] = fmaf(w * r, ev - ov, neq);
+      moving += f[s][2 * k + 1] + f[s][2 * k + 2];
+    }
+    f[s][0] = r - moving;
   }
 }
 
@@ -400,7 +457,7 @@ __device__ __forceinline__ void halo_pos(int h, int& hx, int& hy) {
   else { hx = BXT; hy = h - 2 * EX - ROWS; }
 }
 
-template <Storage S, bool WALLS, Mode M, int BXT, int ROWS, int HW>
+template <Storage S, bool WALLS, Mode M, int BXT, int ROWS, int HW, bool REG>
 __global__ void __launch_bounds__(BXT * ROWS + 64 * HW)
 march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
   using Sh = Shape<BXT, ROWS, HW>;
@@ -495,7 +552,11 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
                 shan_chen_finish<EX>(ring + slot * PLANE, at, cur_S);
                 Local L;
                 make_local(cur_rho[0], cur_rho[1], cur_u, cur_S, ph, L);
-                collide(cur, L, ph);
+                if constexpr (REG) {
+                  collide_regularized(cur, L, ph);
+                } else {
+                  collide(cur, L, ph);
+                }
                 const __amdgpu_buffer_rsrc_t rd = plane_rsrc<T>(io.dst, zc, g);
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
@@ -507,11 +568,11 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
 #pragma unroll
                     for (int i = 1; i < Q; ++i) {
                       const float w_s = ws[s][i <= 6 ? 1 : 2];
-                      const T q = Tr::encode(cur[s][i] - w_s);
-                      decoded += Tr::decode(q) + w_s;
+                      const T q = Tr::sub_encode(cur[s][i], w_s);
+                      decoded += Tr::decode_add(q, w_s);
                       buf_store<T>(q, rd, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
                     }
-                    const T q0 = Tr::encode((cur_rho[s] - decoded) - ws[s][0]);
+                    const T q0 = Tr::sub_encode(cur_rho[s] - decoded, ws[s][0]);
                     buf_store<T>(q0, rd, col_b, static_cast<uint32_t>(s * Q) * ppb);
                   } else {
 #pragma unroll
@@ -759,28 +820,35 @@ int auto_tile(const Grid& g, bool walls, int elem_bytes) {
   return best;
 }
 
-template <Storage S, bool WALLS, Mode M, int BXT, int ROWS, int HW>
+template <Storage S, bool WALLS, Mode M, int BXT, int ROWS, int HW, bool REG = false>
 static hipError_t launch_shape(const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io,
                                hipStream_t st) {
   using Sh = Shape<BXT, ROWS, HW>;
-  hipLaunchKernelGGL((march_kernel<S, WALLS, M, BXT, ROWS, HW>), dim3(t.blocks), dim3(Sh::NT), 0, st, g, ph, t,
-                     io);
+  hipLaunchKernelGGL((march_kernel<S, WALLS, M, BXT, ROWS, HW, REG>), dim3(t.blocks), dim3(Sh::NT), 0, st, g, ph,
+                     t, io);
   return hipGetLastError();
+}
+
+template <Storage S, bool WALLS, bool REG>
+static hipError_t launch_step(const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io, hipStream_t st) {
+  constexpr Mode M = Mode::Step;
+  switch (t.tile) {
+    case 0: return launch_shape<S, WALLS, M, 64, 8, 3, REG>(g, ph, t, io, st);
+    case 1: return launch_shape<S, WALLS, M, 64, 12, 3, REG>(g, ph, t, io, st);
+    case 2: return launch_shape<S, WALLS, M, 32, 16, 2, REG>(g, ph, t, io, st);
+    case 3: return launch_shape<S, WALLS, M, 128, 4, 3, REG>(g, ph, t, io, st);
+    case 4: return launch_shape<S, WALLS, M, 64, 4, 3, REG>(g, ph, t, io, st);
+    case 5: return launch_shape<S, WALLS, M, 256, 2, 3, REG>(g, ph, t, io, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <Storage S, bool WALLS, Mode M>
 static hipError_t launch_tile(const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io,
                               hipStream_t st) {
   if constexpr (M == Mode::Step) {
-    switch (t.tile) {
-      case 0: return launch_shape<S, WALLS, M, 64, 8, 3>(g, ph, t, io, st);
-      case 1: return launch_shape<S, WALLS, M, 64, 12, 3>(g, ph, t, io, st);
-      case 2: return launch_shape<S, WALLS, M, 32, 16, 2>(g, ph, t, io, st);
-      case 3: return launch_shape<S, WALLS, M, 128, 4, 3>(g, ph, t, io, st);
-      case 4: return launch_shape<S, WALLS, M, 64, 4, 3>(g, ph, t, io, st);
-      case 5: return launch_shape<S, WALLS, M, 256, 2, 3>(g, ph, t, io, st);
-      default: return hipErrorInvalidValue;
-    }
+    return ph.regularized ? launch_step<S, WALLS, true>(g, ph, t, io, st)
+                          : launch_step<S, WALLS, false>(g, ph, t, io, st);
   } else if constexpr (M == Mode::Moments) {
     // Diagnostics use one shape (tile 0).
     if (t.tile != 0) return hipErrorInvalidValue;

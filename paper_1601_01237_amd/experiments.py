@@ -15,7 +15,7 @@ densities (the droplet dissolves), so the physical cases default to
 G = -2.6 (|G| rho ~ 2.7 > 2).  With BGK and the exact-difference force the
 step is unstable below tau ~ 0.8 at this coupling.
 
-    python -m paper_1601_01237_amd.experiments laplace|wall|incline [--n N]
+    python -m paper_1601_01237_amd.experiments laplace|wall|incline [--n N] [--collision regularized]
 """
 
 from __future__ import annotations
@@ -32,11 +32,13 @@ from .sim import Sim
 G_PHYS = -2.6
 
 
-def laplace_point(n, radius, tau, G=G_PHYS, steps=4000, width=1.5, seed=2):
-    """One static droplet in a periodic n^3 box.  Returns a dict of results."""
+def laplace_point(n, radius, tau, G=G_PHYS, steps=4000, width=1.5, seed=2, collision="bgk"):
+    """One static droplet in a periodic n^3 box.  ``tau`` is one value or
+    (tau_A, tau_B) (tau_A inside the droplet).  Returns a dict of results."""
     shape = (n, n, n)
     rho0 = inputs.sphere_droplet(shape, radius=radius, seed=seed, width=width)
-    sim = Sim(rho0, tau=(tau, tau), G=G)
+    taus = (tau, tau) if np.isscalar(tau) else tuple(tau)
+    sim = Sim(rho0, tau=taus, G=G, collision=collision)
     m0 = sim.moments(want_fields=False)[2]
     sim.step(steps)
     rho, _, d = sim.moments()
@@ -60,17 +62,18 @@ def laplace_point(n, radius, tau, G=G_PHYS, steps=4000, width=1.5, seed=2):
     return out
 
 
-def laplace_sweep(n=64, radii=(8.0, 10.0, 12.0, 16.0), taus=(0.8, 1.0, 1.5), G=G_PHYS, steps=4000):
+def laplace_sweep(n=64, radii=(8.0, 10.0, 12.0, 16.0), taus=(0.8, 1.0, 1.5), G=G_PHYS, steps=4000,
+                  collision="bgk"):
     """Points and per-tau fits of dP = 2 sigma / R + b."""
     points = []
     fitsd = {}
     for tau in taus:
-        pts = [laplace_point(n, R, tau, G=G, steps=steps) for R in radii]
+        pts = [laplace_point(n, R, tau, G=G, steps=steps, collision=collision) for R in radii]
         points += pts
         good = [q for q in pts if np.isfinite(q["dp"])]
         if len(good) >= 2:
             s, a, b, r2 = fits.laplace_fit([q["R_eq"] for q in good], [q["dp"] for q in good])
-            fitsd[tau] = dict(sigma=s, intercept=b, r2=r2)
+            fitsd[tau if np.isscalar(tau) else "/".join(str(t) for t in tau)] = dict(sigma=s, intercept=b, r2=r2)
     return dict(points=points, fits=fitsd)
 
 
@@ -140,10 +143,11 @@ def main():
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--G", type=float, default=G_PHYS)
+    ap.add_argument("--collision", default="bgk", choices=["bgk", "regularized"])
     args = ap.parse_args()
     if args.case == "laplace":
         radii = tuple(float(r) for r in (np.array([12, 16, 24, 32]) * args.n / 128.0))
-        res = laplace_sweep(n=args.n, radii=radii, G=args.G, steps=args.steps or 5000)
+        res = laplace_sweep(n=args.n, radii=radii, G=args.G, steps=args.steps or 5000, collision=args.collision)
     elif args.case == "wall":
         res = dict(sym=wall_droplet(G=args.G), a=wall_droplet(rho_wall=(0.0, 0.3), G=args.G),
                    b=wall_droplet(rho_wall=(0.3, 0.0), G=args.G))

@@ -45,11 +45,15 @@ class Sim:
     rho_shift : per-species shift of the 16-bit forms; default: mean density.
     solid : optional bool array (nz, ny, nx) of wall cells.
     rho_wall : wall potential rho_s^a (Sec. 4).
+    collision : "bgk" (Eq. 2) or "regularized" (Eqs. 10-11 of Sec. 3).
     tile, zchunk : tiling of the step kernel (results do not depend on it).
     """
 
+    COLLISIONS = {"bgk": _lib.BGK, "regularized": _lib.REGULARIZED}
+
     def __init__(self, rho0, tau=(1.0, 1.0), G=-1.0, storage="fp32", rho_shift=None,
-                 solid=None, rho_wall=(0.0, 0.0), device="cuda:0", tile=None, zchunk=None):
+                 solid=None, rho_wall=(0.0, 0.0), device="cuda:0", tile=None, zchunk=None,
+                 collision="bgk"):
         self.lib = _lib.load()
         self.device = torch.device(device)
         rho0 = torch.as_tensor(np.asarray(rho0, dtype=np.float64))
@@ -78,6 +82,10 @@ class Sim:
                 p.G[a][b] = self.G[a][b]
         p.rho_shift[0], p.rho_shift[1] = self.rho_shift
         p.rho_wall[0], p.rho_wall[1] = self.rho_wall
+        if collision not in self.COLLISIONS:
+            raise ValueError(f"collision must be one of {sorted(self.COLLISIONS)}")
+        self.collision = collision
+        p.collision = self.COLLISIONS[collision]
         self.params = p
 
         # Plane-major state layout with padded population planes (lbm.h).
