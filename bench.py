@@ -65,12 +65,14 @@ def time_steps(sim, steps, warmup):
     return start.elapsed_time(end) / steps  # ms per step (= per launch)
 
 
-def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1.0, tile=None, zchunk=None):
+def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1.0, tile=None, zchunk=None,
+             collision="bgk"):
     from paper_1601_01237_amd import inputs
     from paper_1601_01237_amd.sim import Sim
     if rho0 is None:
         rho0 = inputs.sphere_droplet(shape, radius=shape[0] / 8.0, seed=0)
-    sim = Sim(rho0, tau=(tau, tau), G=G, storage=storage, solid=solid, tile=tile, zchunk=zchunk)
+    sim = Sim(rho0, tau=(tau, tau), G=G, storage=storage, solid=solid, tile=tile, zchunk=zchunk,
+              collision=collision)
     ms = time_steps(sim, steps, warmup)
     _, _, diag = sim.moments(want_fields=False)
     n = int(np.prod(shape))
@@ -141,21 +143,26 @@ def copy_ceiling(gib=4.0, reps=10):
     return 2.0 * n / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(shape, seconds_budget=30.0):
-    """The FP64 oracle on one step of the headline workload (single thread)."""
+def cpu_baseline(shape, seconds_budget=12.0, max_steps=8):
+    """The FP64 oracle on whole steps of the headline workload, one thread.
+
+    Steps until ``seconds_budget`` has passed (at most ``max_steps``); any
+    BLAS the oracle reaches is limited to one thread."""
+    from threadpoolctl import threadpool_limits
     from oracle import lbm as olbm
     from paper_1601_01237_amd import inputs
     rho0 = inputs.sphere_droplet(shape, radius=16.0, seed=0)
     p = olbm.Params(tau=(1.0, 1.0), G=((0.0, -1.0), (-1.0, 0.0)))
     f = olbm.init_state(rho0)
-    t0 = time.perf_counter()
     steps = 0
-    while True:
-        f = olbm.step(f, p)
-        steps += 1
-        if time.perf_counter() - t0 > seconds_budget * 0.5 or steps >= 3:
-            break
-    dt = time.perf_counter() - t0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while True:
+            f = olbm.step(f, p)
+            steps += 1
+            if time.perf_counter() - t0 > seconds_budget or steps >= max_steps:
+                break
+        dt = time.perf_counter() - t0
     n = int(np.prod(shape))
     return dict(value=n * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
                 sample=f"{steps} step(s) of the {shape[2]}x{shape[1]}x{shape[0]} workload, FP64 NumPy, "
@@ -206,6 +213,11 @@ def main():
             print(f"[bench] 512^3 {storage}", file=sys.stderr, flush=True)
             r = run_case(big, storage, steps_big, 5, rho0=rho_big, tau=0.6)
             extra[f"512^3_{storage}"] = {k: round(v, 3) for k, v in r.items() if k != "n"}
+        extra["fp16_over_fp32_512^3"] = round(extra["512^3_fp32"]["ms_per_step"]
+                                              / extra["512^3_fp16"]["ms_per_step"], 3)
+        print("[bench] 512^3 fp32 regularized", file=sys.stderr, flush=True)
+        r = run_case(big, "fp32", steps_big, 5, rho0=rho_big, tau=0.6, collision="regularized")
+        extra["512^3_fp32_regularized"] = {k: round(v, 3) for k, v in r.items() if k != "n"}
         del rho_big
         print("[bench] walls 384x192x192", file=sys.stderr, flush=True)
         rho_w, solid = inputs.inclined_channel((192, 192, 384), angle_deg=30.0, radius=32.0, seed=0)

@@ -193,7 +193,7 @@ adjoint_stream_kernel(const Grid g, const Phys ph, const Tiling tl, const uint32
         const uint32_t fwd_off = col.y[1 + CY[i]] + col.x[1 + CX[i]];
         if constexpr (WALLS) {
           if (i != 0 && ((lk >> opp(i)) & 1u))
-            dst[s][i] = buf_load<float>(rz[1], col_b, static_cast<uint32_t>(s * Q + opp(i)) * ppb);
+            dst[s][i] = buf_load<float, LOAD_BOUNCE>(rz[1], col_b, static_cast<uint32_t>(s * Q + opp(i)) * ppb);
           else
             dst[s][i] = buf_load<float>(rz[1 + CZ[i]], fwd_off, static_cast<uint32_t>(s * Q + i) * ppb);
         } else {

@@ -57,14 +57,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* buf, in
                                            static_cast<int>(block), RSRC_FLAGS);
 }
 
-template <typename T>
+template <typename T, int AUX = 0>
 __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   if constexpr (sizeof(T) == 4) {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
   } else {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, AUX));
   }
 }
+
+// Cache-policy bits of the bounce-back loads (sc0).  A load whose resource or
+// scalar offset depends on a per-lane condition would need a loop over the
+// distinct values; with a different policy than the ordinary pull, the two
+// loads of a population stay separate instructions under a lane mask.
+constexpr int LOAD_BOUNCE = 1;
 
 // Stores carry the non-temporal hint: the new state is not read again in this
 // step, so it should not displace the lines neighbouring workgroups still

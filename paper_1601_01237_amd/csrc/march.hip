@@ -45,7 +45,7 @@ __device__ __forceinline__ void pull_species(const __amdgpu_buffer_rsrc_t rz[3],
     T v;
     if constexpr (WALLS) {
       if ((i != 0) && ((links >> i) & 1u)) {
-        v = buf_load<T>(rz[1], own, static_cast<uint32_t>(s * Q + opp(i)) * ppb);
+        v = buf_load<T, LOAD_BOUNCE>(rz[1], own, static_cast<uint32_t>(s * Q + opp(i)) * ppb);
       } else {
         v = buf_load<T>(rz[1 - CZ[i]], off, static_cast<uint32_t>(s * Q + i) * ppb);
       }
@@ -772,10 +772,11 @@ Tiling make_tiling(const Grid& g, int tile, int zchunk) {
   t.tiles_y = (g.ny + sh.rows - 1) / sh.rows;
   const long long txy = static_cast<long long>(t.tiles_x) * t.tiles_y;
   if (zchunk <= 0) {
-    // One workgroup fills a CU; march 16 to 64 planes, so that the two planes
-    // each workgroup re-reads at the ends of its column cost at most 1/8, with
-    // at least about two workgroups per CU (256 CUs) over the launch.  Small
-    // grids go down to 8 planes to keep one workgroup per CU.
+    // One workgroup fills a CU; march as many planes as leave about two
+    // workgroups per CU (256 CUs) over the launch, so that the planes each
+    // workgroup re-reads at the ends of its column cost little (measured at
+    // 512^3: 256 planes beat 64 by 1.5-2%).  Small grids go down to 8 planes
+    // to keep one workgroup per CU.
     const long long cols = static_cast<long long>(g.nz) * txy;
     long long zc = (cols + 511) / 512;
     if (zc < 16) {
@@ -783,7 +784,7 @@ Tiling make_tiling(const Grid& g, int tile, int zchunk) {
       if (zc < 8) zc = 8;
       if (zc > 16) zc = 16;
     }
-    if (zc > 64) zc = 64;
+    if (zc > 256) zc = 256;
     if (zc > g.nz) zc = g.nz;
     zchunk = static_cast<int>(zc);
   }
