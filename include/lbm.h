@@ -205,8 +205,9 @@ lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
  * 3 = 128x4, 4 = 64x4, 5 = 256x2; -1 (the default) picks, among 128x4, 64x8
  * and 32x16 (64x8 and 32x16 with walls or 16-bit storage), the one that pads
  * the x-y plane least, the first listed on a tie.  Results do not depend on this choice (bitwise).
- * The adjoint march uses the same setting when it is 0, 2 or 4, else the
- * automatic choice with walls; diagnostics use 64x8.  Host-side setting. */
+ * The adjoint march uses the same setting when it is 0, 2 or 4, else 64x4
+ * with walls and the automatic choice among 64x8 and 32x16 without;
+ * diagnostics use 64x8.  Host-side setting. */
 lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t tile, int32_t zchunk);
 
 /* ---- Adjoint (reverse mode) of one step, FP32 storage and BGK only -----

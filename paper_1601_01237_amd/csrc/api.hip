@@ -40,7 +40,10 @@ Tiling step_tiling(const lbm_ctx* c) {
 }
 Tiling aux_tiling(const lbm_ctx* c) { return make_tiling(c->g, 0, 0); }
 Tiling adjoint_tiling(const lbm_ctx* c) {
-  const int tile = adjoint_shape(c->tile) ? c->tile : auto_tile(c->g, true, 4);
+  // With walls the adjoint march needs about 200 registers: the 64x4 shape
+  // (7 waves) holds them without spilling, the 10- and 11-wave shapes do not.
+  const int automatic = c->links ? 4 : auto_tile(c->g, true, 4);
+  const int tile = adjoint_shape(c->tile) ? c->tile : automatic;
   return make_tiling(c->g, tile, c->tile == tile ? c->zchunk : 0);
 }
 

@@ -6,6 +6,9 @@
   interface (Sec. 4.2.2) and drift of the droplet's centre of mass.
 * Droplet on an inclined wall (Sec. 4.2.3): drift velocity from the change of
   the droplet's centre of mass over a window of steps.
+* Spurious velocity of static droplets with unequal relaxation times inside
+  and outside (Sec. 3), and contact angle / wall film against the
+  dimensionless wall potential alpha (Sec. 4.2.2).
 
 Every time step runs in liblbm.so; this module only sets up inputs, calls the
 library and fits the reduced results on the host (:mod:`.fits`).
@@ -15,7 +18,8 @@ densities (the droplet dissolves), so the physical cases default to
 G = -2.6 (|G| rho ~ 2.7 > 2).  With BGK and the exact-difference force the
 step is unstable below tau ~ 0.8 at this coupling.
 
-    python -m paper_1601_01237_amd.experiments laplace|wall|incline [--n N] [--collision regularized]
+    python -m paper_1601_01237_amd.experiments laplace|wall|incline|spurious|wetting [--n N]
+        [--collision regularized]
 """
 
 from __future__ import annotations
@@ -77,6 +81,45 @@ def laplace_sweep(n=64, radii=(8.0, 10.0, 12.0, 16.0), taus=(0.8, 1.0, 1.5), G=G
     return dict(points=points, fits=fitsd)
 
 
+def spurious_sweep(n=64, radii=(8.0, 12.0, 16.0), tau_pairs=((0.8, 0.8), (0.7, 1.5), (1.5, 0.7)),
+                   G=-2.3, steps=4000, collision="regularized"):
+    """Static droplets with tau inside / outside (Sec. 3): per pair the
+    Laplace fit and the largest spurious velocity max |u_F| over the radii."""
+    out = {}
+    for pair in tau_pairs:
+        pts = [laplace_point(n, R, pair, G=G, steps=steps, collision=collision) for R in radii]
+        key = f"{pair[0]}/{pair[1]}"
+        good = [q for q in pts if np.isfinite(q["dp"])]
+        rec = dict(max_uf=max(q["max_uf"] for q in pts), nonfinite=sum(q["nonfinite"] for q in pts),
+                   points=pts)
+        if len(good) >= 2:
+            sig, _, b, r2 = fits.laplace_fit([q["R_eq"] for q in good], [q["dp"] for q in good])
+            rec.update(sigma=sig, intercept=b, r2=r2)
+        out[key] = rec
+    return out
+
+
+def wall_potential(alpha, rho0):
+    """Wall potentials (rho_s^A, rho_s^B) from a dimensionless wettability
+    alpha (Sec. 4.2.2): the wetting species gets rho0 |alpha|, the other 0.
+    Species A (the droplet) plays the paper's second component, so alpha > 0
+    makes the wall wet by the droplet."""
+    return (rho0 * max(alpha, 0.0), rho0 * max(-alpha, 0.0))
+
+
+def wetting_sweep(alphas=(-0.3, -0.15, 0.0, 0.15, 0.3), rho0=1.0, G=G_PHYS, tau=1.0, steps=4000,
+                  collision="bgk"):
+    """Contact angle and wall-film density of a droplet on a flat wall against
+    the wettability alpha (Sec. 4.2.2).  rho0 is the bulk density the
+    potentials are scaled by (the paper's 0.22 is its own initial density)."""
+    out = []
+    for a in alphas:
+        r = wall_droplet(rho_wall=wall_potential(a, rho0), G=G, tau=tau, steps=steps, collision=collision)
+        out.append(dict(alpha=a, theta=r["theta"], film_rho_a=r["film_rho_a"], nonfinite=r["nonfinite"],
+                        drift=r["drift"]))
+    return out
+
+
 def droplet_com(rho_a, mask, thr):
     """Centre of mass (x, y, z) of cells with rho_A > thr inside ``mask`` (no wrap)."""
     sel = mask & (rho_a > thr)
@@ -85,11 +128,11 @@ def droplet_com(rho_a, mask, thr):
 
 
 def wall_droplet(shape=(40, 96, 96), radius=14.0, rho_wall=(0.0, 0.0), G=G_PHYS, tau=1.0, steps=4000,
-                 window=1000):
+                 window=1000, collision="bgk"):
     """Hemispherical droplet on the flat wall z = 0 of a channel (walls at z = 0, nz-1)."""
     nz, ny, nx = shape
     rho0, solid = inputs.flat_channel(shape, seed=3, radius=radius)
-    sim = Sim(rho0, tau=(tau, tau), G=G, solid=solid, rho_wall=rho_wall)
+    sim = Sim(rho0, tau=(tau, tau), G=G, solid=solid, rho_wall=rho_wall, collision=collision)
     zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     cap = (np.hypot(xx - nx / 2.0, yy - ny / 2.0) < 2.5 * radius) & (zz <= nz // 2) & (zz >= 1)
     sim.step(steps - window)
@@ -139,7 +182,7 @@ def incline_drift(shape=(192, 192, 384), angle=30.0, radius=32.0, G=G_PHYS, tau=
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("case", choices=["laplace", "wall", "incline"])
+    ap.add_argument("case", choices=["laplace", "wall", "incline", "spurious", "wetting"])
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--G", type=float, default=G_PHYS)
@@ -151,6 +194,10 @@ def main():
     elif args.case == "wall":
         res = dict(sym=wall_droplet(G=args.G), a=wall_droplet(rho_wall=(0.0, 0.3), G=args.G),
                    b=wall_droplet(rho_wall=(0.3, 0.0), G=args.G))
+    elif args.case == "spurious":
+        res = spurious_sweep(n=args.n, steps=args.steps or 4000, collision=args.collision)
+    elif args.case == "wetting":
+        res = wetting_sweep(G=args.G, steps=args.steps or 4000, collision=args.collision)
     else:
         res = incline_drift(G=args.G, steps=args.steps or 10000)
     print(json.dumps(res, default=float))

@@ -50,3 +50,12 @@ def test_sphere_fit_and_contact_angle():
 def test_drift_velocity_wraps_periodically():
     v, d = fits.drift_velocity([1.0, 5.0, 2.0], [99.0, 5.0, 2.0], 10, lengths=(100.0, 100.0, 50.0))
     assert abs(v - 0.2) < 1e-12 and abs(d[0] + 0.2) < 1e-12
+
+
+def test_wall_potential_parameterisation():
+    from paper_1601_01237_amd.experiments import wall_potential
+    assert wall_potential(0.0, 0.22) == (0.0, 0.0)
+    a, b = wall_potential(0.4, 0.22)
+    assert abs(a - 0.088) < 1e-15 and b == 0.0          # the paper's 40-degree slug value
+    a, b = wall_potential(-0.5, 1.0)
+    assert a == 0.0 and b == 0.5
