@@ -1,6 +1,9 @@
 """Counter runs and their summaries for the fused step (rocprofv3 helpers).
 
-Three subcommands:
+Four subcommands:
+
+``run-adjoint``
+    Forward then reverse steps of the differentiation workload (n^3 droplet).
 
 ``run``
     The program profiled: the library's reference streaming copy
@@ -95,6 +98,26 @@ def cmd_run(args):
     torch.cuda.synchronize()
     sim.close()
     print(f"[profiling] {args.workload} {args.storage}: {args.steps} steps of {shape}", flush=True)
+
+
+def cmd_run_adjoint(args):
+    """Forward steps and reverse steps of the 96^3 differentiation workload."""
+    import torch
+    from . import inputs
+    from .autograd import Reverse
+    from .sim import Sim
+    n = args.n
+    rho0 = inputs.sphere_droplet((n, n, n), radius=20.0 * n / 96.0, seed=0)
+    sim = Sim(rho0, tau=(1.0, 1.0), G=-1.0)
+    sim.step(args.steps)
+    rev = Reverse(sim)
+    lam = rev.seed(torch.ones((2, n, n, n), dtype=torch.float32, device=sim.device))
+    x_t = sim.state.clone()
+    for _ in range(args.steps):
+        lam, _ = rev.step(x_t, lam)
+    torch.cuda.synchronize()
+    sim.close()
+    print(f"[profiling] adjoint {n}^3: {args.steps} forward and {args.steps} reverse steps", flush=True)
 
 
 def _rows(path, counter):
@@ -203,6 +226,9 @@ def main(argv=None):
     r.add_argument("--steps", type=int, default=5)
     r.add_argument("--copy-gib", type=float, default=2.0)
     r.add_argument("--copy-reps", type=int, default=3)
+    ra = sub.add_parser("run-adjoint")
+    ra.add_argument("--n", type=int, default=96)
+    ra.add_argument("--steps", type=int, default=20)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -220,7 +246,7 @@ def main(argv=None):
     s.add_argument("--command", default="")
     s.add_argument("--bench", default=None)
     args = ap.parse_args(argv)
-    {"run": cmd_run, "traffic": cmd_traffic, "stats": cmd_stats}[args.cmd](args)
+    {"run": cmd_run, "run-adjoint": cmd_run_adjoint, "traffic": cmd_traffic, "stats": cmd_stats}[args.cmd](args)
 
 
 if __name__ == "__main__":
