@@ -110,3 +110,48 @@ def test_plane_stride_and_state_size(lib):
     assert lib.lbm_plane_stride(0, 4, _lib.FP32) == -1
     assert lib.lbm_plane_stride(4, 4, 3) == -1
     assert lib.lbm_state_elems(4, 4, 0, _lib.FP32) == -1
+
+
+def _valid_params(_lib):
+    p = _lib.Params()
+    p.nx, p.ny, p.nz = 8, 8, 8
+    p.storage = _lib.FP32
+    p.tau[0], p.tau[1] = 1.0, 1.0
+    p.G[0][1] = p.G[1][0] = -1.0
+    p.collision = _lib.BGK
+    return p
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("tau", (0.5, 1.0), -1),            # tau must exceed 1/2 (Eq. 2)
+    ("tau", (1.0, float("nan")), -1),
+    ("G", ((0.5, -1.0), (-1.0, 0.0)), -5),   # self-interaction G^{aa} != 0 (Sec. 2)
+    ("storage", 3, -1),
+    ("collision", 2, -1),
+    ("nx", 0, -1),
+    ("rho_wall", (float("inf"), 0.0), -1),
+])
+def test_invalid_parameters_are_rejected_before_any_device_call(lib, field, value, status):
+    """lbm_init validates its parameters synchronously, before it allocates or
+    launches anything; the dummy device pointers are never touched."""
+    from paper_1601_01237_amd import _lib
+    p = _valid_params(_lib)
+    if field in ("tau", "rho_wall"):
+        getattr(p, field)[0], getattr(p, field)[1] = value
+    elif field == "G":
+        for a in range(2):
+            for b in range(2):
+                p.G[a][b] = value[a][b]
+    else:
+        setattr(p, field, value)
+    ctx = ctypes.c_void_p()
+    dummy_a, dummy_b, dummy_rho = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), dummy_a, dummy_b, None, dummy_rho, None) == status
+    assert ctx.value is None
+
+
+def test_status_of_calls_on_a_null_context(lib):
+    assert lib.lbm_set_tiling(None, -1, 0) == -1
+    assert lib.lbm_moments(None, None, None, None, None) == -1
+    assert lib.lbm_adjoint_seed(None, None, None) == -1
+    assert lib.lbm_destroy(None) == 0

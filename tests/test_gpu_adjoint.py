@@ -161,3 +161,37 @@ def test_calibration_gradient_against_central_differences(lib):
     assert abs(float(Tt.grad) - fd_t) <= 1e-2 * abs(fd_t), (float(Tt.grad), fd_t)
     ad_r = float((r0.grad * v).sum())
     assert abs(ad_r - fd_r) <= 1e-2 * abs(fd_r), (ad_r, fd_r)
+
+
+def test_adjoint_step_96cube_all_cells(lib):
+    """One reverse step of the differentiation workload at its full size
+    (96^3 droplet, R = 20, tau = 1, G = -1, automatic tiling as timed),
+    every cell against the oracle."""
+    from paper_1601_01237_amd.autograd import Reverse, from_plane_major, to_plane_major
+    from paper_1601_01237_amd.sim import Sim
+    say("adjoint one step 96^3")
+    n = 96
+    rho0 = inputs.sphere_droplet((n, n, n), radius=20.0, seed=0)
+    p = olbm.Params(tau=(1.0, 1.0), G=((0.0, -1.0), (-1.0, 0.0)))
+    sim = Sim(rho0, tau=p.tau, G=p.G)
+    sim.step(20)
+    f = sim.populations().cpu().numpy().astype(np.float64)   # pre-collision f at t = 20
+    lam1 = np.random.default_rng(9).normal(size=f.shape).astype(np.float32)
+    rev = Reverse(sim)
+    lam_gpu, drho = rev.step(sim.state, to_plane_major(torch.from_numpy(lam1).cuda(), sim), want_drho0=True)
+    got = from_plane_major(lam_gpu, sim).cpu().numpy()
+    d = rev.dparams.cpu().numpy()
+    sim.close()
+    mu, dG, dtau = oadj.collide_adjoint(f, lam1.astype(np.float64), p)
+    want = oadj.stream_adjoint(mu)
+    e = rel_err(got, want)
+    say(f"96^3 adjoint step: lam error {e:.2e}, dG {d[0]:.6e} vs {dG[0, 1] + dG[1, 0]:.6e}")
+    assert e < 1e-5, e
+    m = olbm.macroscopic(f, p)
+    scale_tau = [np.sum(np.abs(lam1[a] * (f[a] - olbm.equilibrium(m["rho_s"][a], m["u"])))) / p.tau[a] ** 2
+                 for a in range(2)]
+    assert abs(d[0] - (dG[0, 1] + dG[1, 0])) <= 1e-4 * abs(dG[0, 1] + dG[1, 0]), (d[0], dG)
+    assert abs(d[1] - dtau[0]) <= 1e-6 * scale_tau[0]
+    assert abs(d[2] - dtau[1]) <= 1e-6 * scale_tau[1]
+    e = rel_err(drho.view(2, n, n, n).cpu().numpy(), np.einsum("i,aizyx->azyx", olbm.W, mu))
+    assert e < 1e-5, e
