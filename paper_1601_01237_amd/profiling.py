@@ -54,8 +54,14 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def workload(name, storage):
+def workload(name, storage, collision="bgk"):
     """(shape, kwargs of Sim) of a named benchmark workload."""
+    shape, kw = _workload(name, storage)
+    kw["collision"] = collision
+    return shape, kw
+
+
+def _workload(name, storage):
     from . import inputs
     if name == "128":
         shape = (128, 128, 128)
@@ -92,7 +98,7 @@ def cmd_run(args):
     torch.cuda.synchronize()
     del src, dst
     print(f"[profiling] copied {args.copy_reps} x {n} bytes", flush=True)
-    shape, kw = workload(args.workload, args.storage)
+    shape, kw = workload(args.workload, args.storage, args.collision)
     sim = Sim(**kw)
     sim.step(args.steps)
     torch.cuda.synchronize()
@@ -224,6 +230,7 @@ def main(argv=None):
     r.add_argument("--workload", default="128", choices=["128", "512", "walls"])
     r.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
     r.add_argument("--steps", type=int, default=5)
+    r.add_argument("--collision", default="bgk", choices=["bgk", "regularized"])
     r.add_argument("--copy-gib", type=float, default=2.0)
     r.add_argument("--copy-reps", type=int, default=3)
     ra = sub.add_parser("run-adjoint")
