@@ -28,9 +28,14 @@
  *             the current state lives in buf_a if t is even, buf_b if odd.
  *             Stored states and adjoint arrays use the plane-major layout
  *             X[z][a][i][y][x]: element (a, i, x, y, z) at index
- *             ((z*2 + a)*19 + i)*S + y*nx + x with the plane stride
+ *             ((z*2 + a)*19 + i)*S + y*nx + pos(x) with the plane stride
  *             S = lbm_plane_stride(nx, ny, storage) >= nx*ny, so that one z
- *             plane of all 38 populations is one contiguous block.  The S -
+ *             plane of all 38 populations is one contiguous block.  pos(x)
+ *             = x, except for the 16-bit storage forms with even nx and no
+ *             walls, whose rows are folded: with h = nx/2 (lbm_row_half),
+ *             pos(x) = 2x for
+ *             x < h and 2(x - h) + 1 for x >= h, so the 32-bit word k of a
+ *             row holds cells k and k + h.  The S -
  *             nx*ny elements after each plane are padding (never read):
  *             population planes a large power of two apart would map the rows
  *             a step reads together onto the same DRAM channels.  A state (or
@@ -150,6 +155,12 @@ const char *lbm_status_str(lbm_status s);
  * library does not support.  Pure host call. */
 int64_t lbm_plane_stride(int32_t nx, int32_t ny, int32_t storage);
 
+/* h = nx/2 when rows of storage `storage` are folded (16-bit forms, even
+ * nx, walls == 0; see pos(x) above), 0 when rows are stored in x order, -1
+ * for nx < 1 or an unknown storage.  `walls` is nonzero when the context is
+ * created with a solid mask.  Pure host call. */
+int32_t lbm_row_half(int32_t nx, int32_t storage, int32_t walls);
+
 /* Elements of one state buffer (buf_a, buf_b, x_t) of storage `storage`, and
  * of one adjoint array (lam) with storage LBM_FP32: 2*19*nz*plane stride.
  * Returns -1 for unsupported sizes.  Pure host call. */
@@ -201,10 +212,15 @@ lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
 
 /* Tiling of the fused step kernel: workgroup tile shape and the number of z
  * planes each workgroup marches through (>= 1; 0 picks a default from the
- * grid).  Shapes (cells in x by y): 0 = 64x8, 1 = 64x12, 2 = 32x16,
- * 3 = 128x4, 4 = 64x4, 5 = 256x2; -1 (the default) picks, among 128x4, 64x8
- * and 32x16 (64x8 and 32x16 with walls or 16-bit storage), the one that pads
- * the x-y plane least, the first listed on a tie.  Results do not depend on this choice (bitwise).
+ * grid).  Shapes with one cell per lane (cells in x by y): 0 = 64x8,
+ * 1 = 64x12, 2 = 32x16, 3 = 128x4, 4 = 64x4, 5 = 256x2.  Shapes with one
+ * folded 32-bit word (two cells) per lane, for 16-bit storage with folded
+ * rows and no walls only (else LBM_EINVAL), in words by rows: 6 = 64x8,
+ * 7 = 32x16, 8 = 32x8, 9 = 32x12.  -1 (the default) picks, among 8 and 9 for
+ * folded 16-bit rows without walls, else among 128x4, 64x8 and 32x16 (64x8
+ * and 32x16 with walls or 16-bit storage), the one that pads the x-y plane
+ * least, the first listed on a tie.  Results do not depend on this choice
+ * (bitwise).
  * The adjoint march uses the same setting when it is 0, 2 or 4, else 64x4
  * with walls and the automatic choice among 64x8 and 32x16 without;
  * diagnostics use 64x8.  Host-side setting. */

@@ -56,6 +56,7 @@ def _declare(lib):
         "lbm_status_str": (C.c_char_p, [i32]),
         "lbm_plane_stride": (i64, [i32, i32, i32]),
         "lbm_state_elems": (i64, [i32, i32, i32, i32]),
+        "lbm_row_half": (i32, [i32, i32, i32]),
         "lbm_init": (i32, [C.POINTER(vp), C.POINTER(Params), vp, vp, vp, vp, vp]),
         "lbm_step": (i32, [vp, i64]),
         "lbm_moments": (i32, [vp, vp, vp, vp, C.POINTER(DiagRegion)]),
@@ -95,7 +96,7 @@ def check(func, code):
 
 
 EXPORTED = ["lbm_version", "lbm_velocity_set", "lbm_status_str", "lbm_plane_stride",
-            "lbm_state_elems", "lbm_init", "lbm_step",
+            "lbm_state_elems", "lbm_row_half", "lbm_init", "lbm_step",
             "lbm_moments", "lbm_get_populations", "lbm_set_populations", "lbm_time",
             "lbm_set_time", "lbm_set_tiling", "lbm_adjoint_work_bytes", "lbm_adjoint_step",
             "lbm_adjoint_seed", "lbm_stream_copy", "lbm_destroy"]

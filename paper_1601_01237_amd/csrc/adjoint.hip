@@ -171,7 +171,7 @@ adjoint_stream_kernel(const Grid g, const Phys ph, const Tiling tl, const uint32
   const bool owner = ex < g.nx && ey < g.ny;
   const Column col = make_column<float>(ex, ey, g);
   const uint32_t col_b = col.y[1] + col.x[1];
-  const uint32_t col_off = col_b / 4u;
+  const uint32_t col_off = col.cell;
   const int at = (ty + 1) * EX + tx + 1;
   const uint32_t ppb = g.pstride * 4u;
   const float keep[2] = {1.0f - ph.omega[0], 1.0f - ph.omega[1]};

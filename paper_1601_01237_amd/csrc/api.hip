@@ -101,6 +101,11 @@ int64_t lbm_plane_stride(int32_t nx, int32_t ny, int32_t storage) {
   return plane_stride(nx, ny, static_cast<int>(es));
 }
 
+int32_t lbm_row_half(int32_t nx, int32_t storage, int32_t walls) {
+  if (nx < 1 || storage < LBM_FP32 || storage > LBM_BF16) return -1;
+  return (storage != LBM_FP32 && nx % 2 == 0 && !walls) ? nx / 2 : 0;
+}
+
 int64_t lbm_state_elems(int32_t nx, int32_t ny, int32_t nz, int32_t storage) {
   const int64_t s = lbm_plane_stride(nx, ny, storage);
   if (s < 0 || nz < 1) return -1;
@@ -134,7 +139,10 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) return LBM_EHIP;
   c->p = *p;
-  c->g = Grid{p->nx, p->ny, p->nz, static_cast<uint32_t>(nxy), n, pstride};
+  // 16-bit rows with even nx and no walls are stored folded (two cells per
+  // 32-bit word, stepped by the paired march).
+  const uint32_t half = static_cast<uint32_t>(lbm_row_half(p->nx, p->storage, solid != nullptr));
+  c->g = Grid{p->nx, p->ny, p->nz, static_cast<uint32_t>(nxy), n, pstride, half};
   for (int a = 0; a < 2; ++a) {
     c->ph.omega[a] = static_cast<float>(1.0 / p->tau[a]);
     c->ph.rho_wall[a] = static_cast<float>(p->rho_wall[a]);
@@ -259,6 +267,8 @@ lbm_status lbm_set_time(lbm_ctx* c, int64_t t) {
 
 lbm_status lbm_set_tiling(lbm_ctx* c, int32_t tile, int32_t zchunk) {
   if (!c || tile < -1 || tile >= TILE_SHAPES || zchunk < 0) return LBM_EINVAL;
+  // The paired march needs folded 16-bit rows and no walls.
+  if (pair_shape(tile) && (c->g.half == 0 || c->links != nullptr)) return LBM_EINVAL;
   c->tile = tile;
   c->zchunk = zchunk;
   return LBM_OK;

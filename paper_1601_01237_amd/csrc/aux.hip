@@ -37,10 +37,12 @@ __device__ __forceinline__ uint64_t shifted(const Coord& p, int dx, int dy, int 
 }
 
 // Plane-major index of population (s, i) at cell (x, y, z) + (dx, dy, dz):
-// X[z][s][i][y][x], i.e. ((z * 2 + s) * 19 + i) * pstride + y * nx + x.
+// X[z][s][i][y][pos(x)], i.e. ((z * 2 + s) * 19 + i) * pstride + y * nx +
+// pos(x), with pos the row position of the storage form (folded 16-bit rows).
+template <typename T>
 __device__ __forceinline__ uint64_t pm_at(int s, int i, const Coord& p, int dx, int dy, int dz, const Grid& g) {
   const uint64_t x = wrap_u(p.x + dx, g.nx), y = wrap_u(p.y + dy, g.ny), z = wrap_u(p.z + dz, g.nz);
-  return ((z * 2 + s) * Q + i) * g.pstride + y * g.nx + x;
+  return ((z * 2 + s) * Q + i) * g.pstride + y * g.nx + row_pos<T>(static_cast<int>(x), g);
 }
 
 // Canonical SoA index (s * 19 + i) * N + c of the FP32 population interface.
@@ -83,7 +85,7 @@ __global__ void init_kernel(const Grid g, const Phys ph, const uint32_t* __restr
           v = static_cast<float>(weight_d(i) * rho0[s * g.n + src]);
         }
         if constexpr (Tr::shifted) v -= wshift(ph, s, i);
-        dst[pm_at(s, i, p, 0, 0, 0, g)] = Tr::encode(v);
+        dst[pm_at<typename Tr::T>(s, i, p, 0, 0, 0, g)] = Tr::encode(v);
       }
     }
   }
@@ -105,7 +107,7 @@ __global__ void get_pop_kernel(const Grid g, const Phys ph, const uint32_t* __re
         float v = 0.0f;
         if (!solid) {
           const bool bb = (i != 0) && ((lk >> i) & 1u);
-          const uint64_t at = bb ? pm_at(s, opp(i), p, 0, 0, 0, g) : pm_at(s, i, p, -CX[i], -CY[i], -CZ[i], g);
+          const uint64_t at = bb ? pm_at<typename Tr::T>(s, opp(i), p, 0, 0, 0, g) : pm_at<typename Tr::T>(s, i, p, -CX[i], -CY[i], -CZ[i], g);
           v = Tr::decode(src[at]);
           if constexpr (Tr::shifted) v += wshift(ph, s, i);
         }
@@ -136,7 +138,7 @@ __global__ void set_pop_kernel(const Grid g, const Phys ph, const uint32_t* __re
           v = f[soa(s, pop, at, g)];
         }
         if constexpr (Tr::shifted) v -= wshift(ph, s, j);
-        dst[pm_at(s, j, p, 0, 0, 0, g)] = Tr::encode(v);
+        dst[pm_at<typename Tr::T>(s, j, p, 0, 0, 0, g)] = Tr::encode(v);
       }
     }
   }

@@ -20,11 +20,29 @@ __device__ __forceinline__ int wrap(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Position of cell x inside a stored row.  The 16-bit forms with even nx
+// fold each row: the 32-bit word k holds cells k and k + nx/2 (x < nx/2 at
+// element 2x, x >= nx/2 at element 2(x - nx/2) + 1), so that one aligned
+// 32-bit load brings two cells whose x neighbours sit in the neighbouring
+// words.  FP32 rows and odd nx are stored in x order.
+template <typename T>
+__device__ __forceinline__ uint32_t row_pos(int gx, const Grid& g) {
+  if constexpr (sizeof(T) == 2) {
+    if (g.half) {
+      const uint32_t x = static_cast<uint32_t>(gx);
+      return x < g.half ? 2u * x : 2u * (x - g.half) + 1u;
+    }
+  }
+  return static_cast<uint32_t>(gx);
+}
+
 // Wrapped coordinates of one cell column (x, y) and of its x/y neighbours,
-// as BYTE offsets inside one population plane (nx * ny elements).
+// as BYTE offsets inside one population plane (nx * ny elements), and the
+// column's cell index y * nx + x.
 struct Column {
-  uint32_t x[3];  // (x-1, x, x+1) * sizeof(T)
+  uint32_t x[3];  // row positions of (x-1, x, x+1), times sizeof(T)
   uint32_t y[3];  // ((y-1), y, (y+1)) * nx * sizeof(T)
+  uint32_t cell;  // y * nx + x
 };
 
 template <typename T>
@@ -32,14 +50,15 @@ __device__ __forceinline__ Column make_column(int ex, int ey, const Grid& g) {
   const int gx = wrap(ex, g.nx), gy = wrap(ey, g.ny);
   const uint32_t sz = sizeof(T);
   Column c;
-  c.x[0] = (gx == 0 ? g.nx - 1 : gx - 1) * sz;
-  c.x[1] = gx * sz;
-  c.x[2] = (gx == g.nx - 1 ? 0 : gx + 1) * sz;
+  c.x[0] = row_pos<T>(gx == 0 ? g.nx - 1 : gx - 1, g) * sz;
+  c.x[1] = row_pos<T>(gx, g) * sz;
+  c.x[2] = row_pos<T>(gx == g.nx - 1 ? 0 : gx + 1, g) * sz;
   const int ym = gy == 0 ? g.ny - 1 : gy - 1;
   const int yp = gy == g.ny - 1 ? 0 : gy + 1;
   c.y[0] = static_cast<uint32_t>(ym) * g.nx * sz;
   c.y[1] = static_cast<uint32_t>(gy) * g.nx * sz;
   c.y[2] = static_cast<uint32_t>(yp) * g.nx * sz;
+  c.cell = static_cast<uint32_t>(gy) * g.nx + static_cast<uint32_t>(gx);
   return c;
 }
 

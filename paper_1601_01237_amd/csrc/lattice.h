@@ -55,6 +55,14 @@ template <> struct StorageTraits<Storage::F16> {
   __device__ static inline _Float16 encode(float v) { return static_cast<_Float16>(v); }
   __device__ static inline float decode_add(_Float16 v, float ws) { return decode(v) + ws; }
   __device__ static inline _Float16 sub_encode(float x, float ws) { return encode(x - ws); }
+  // Halves of a 32-bit word of a folded row, and the bits of one value.
+  __device__ static inline float lo(uint32_t w) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w & 0xffffu)));
+  }
+  __device__ static inline float hi(uint32_t w) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w >> 16)));
+  }
+  __device__ static inline uint32_t bits(_Float16 q) { return __builtin_bit_cast(uint16_t, q); }
 };
 
 // bfloat16 kept as its bit pattern: the upper half of an IEEE binary32.
@@ -68,6 +76,9 @@ template <> struct StorageTraits<Storage::BF16> {
   __device__ static inline uint16_t encode(float v) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v)); }
   __device__ static inline float decode_add(uint16_t v, float ws) { return decode(v) + ws; }
   __device__ static inline uint16_t sub_encode(float x, float ws) { return encode(x - ws); }
+  __device__ static inline float lo(uint32_t w) { return __uint_as_float(w << 16); }
+  __device__ static inline float hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+  __device__ static inline uint32_t bits(uint16_t q) { return q; }
 };
 
 }  // namespace lbm

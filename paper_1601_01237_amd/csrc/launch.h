@@ -14,6 +14,7 @@ struct Grid {
   uint32_t nxy;      // nx * ny
   uint64_t n;        // nx * ny * nz
   uint32_t pstride;  // elements from one population plane to the next (>= nxy, padded)
+  uint32_t half;     // nx / 2 when rows of the 16-bit forms are folded (even nx), else 0
 };
 
 // Elements per population plane of the stored state for a storage element
@@ -38,8 +39,11 @@ struct Tiling {
   int blocks;
 };
 
-// Tile shapes: 0 = 64x8, 1 = 64x12, 2 = 32x16, 3 = 128x4, 4 = 64x4, 5 = 256x2 cells.
-constexpr int TILE_SHAPES = 6;
+// Tile shapes: 0 = 64x8, 1 = 64x12, 2 = 32x16, 3 = 128x4, 4 = 64x4, 5 = 256x2 cells
+// (one cell per lane); 6 = 64x8, 7 = 32x16, 8 = 32x8, 9 = 32x12 words of a
+// folded 16-bit row (two cells per lane; 16-bit storage, even nx, no walls).
+constexpr int TILE_SHAPES = 10;
+constexpr bool pair_shape(int tile) { return tile >= 6 && tile < TILE_SHAPES; }
 // Shapes the adjoint march is built for.
 constexpr bool adjoint_shape(int tile) { return tile == 0 || tile == 2 || tile == 4; }
 Tiling make_tiling(const Grid& g, int tile, int zchunk);
@@ -70,6 +74,9 @@ struct MarchIO {
 
 hipError_t launch_march(Storage s, Mode mode, const Grid& g, const Phys& ph, const Tiling& t,
                         const MarchIO& io, hipStream_t st);
+// Step of the 16-bit forms on folded rows (pair shapes 6..9, no walls).
+hipError_t launch_pair_step(Storage s, const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io,
+                            hipStream_t st);
 
 hipError_t launch_init(Storage s, const Grid& g, const Phys& ph, const uint32_t* links,
                        const double* rho0, void* dst, hipStream_t st);

@@ -24,6 +24,7 @@
 // x and y and share that XCD's L2 for the halo re-reads.
 
 #include "buffer.h"
+#include "cell.h"
 #include "launch.h"
 
 namespace lbm {
@@ -33,12 +34,18 @@ namespace lbm {
 // byte size of one population plane, so population (a, i) of a plane starts
 // at (19 a + i) * pp.  Every load is scalar resource + scalar population
 // offset + per-lane (y, x) offset.
+//
+// Returns the species' stored sum D: rho^a itself for FP32; for the shifted
+// 16-bit forms the sum of the stored deviations X_i - w_i rho_shift, so that
+// rho^a = D + rho_shift (the weights sum to one) and the store can keep the
+// stored sum of a cell equal to D.  Both sums run in direction order.
 template <Storage S, bool WALLS>
-__device__ __forceinline__ void pull_species(const __amdgpu_buffer_rsrc_t rz[3], uint32_t ppb, const Column& c,
-                                             uint32_t links, const float ws[3], int s, float f[Q]) {
+__device__ __forceinline__ float pull_species(const __amdgpu_buffer_rsrc_t rz[3], uint32_t ppb, const Column& c,
+                                              uint32_t links, const float ws[3], int s, float f[Q]) {
   using Tr = StorageTraits<S>;
   using T = typename Tr::T;
   const uint32_t own = c.y[1] + c.x[1];
+  float d = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const uint32_t off = c.y[1 - CY[i]] + c.x[1 - CX[i]];
@@ -52,231 +59,22 @@ __device__ __forceinline__ void pull_species(const __amdgpu_buffer_rsrc_t rz[3],
     } else {
       v = buf_load<T>(rz[1 - CZ[i]], off, static_cast<uint32_t>(s * Q + i) * ppb);
     }
+    const float x = Tr::decode(v);
+    d = i == 0 ? x : d + x;
     if constexpr (Tr::shifted) {
-      f[i] = Tr::decode_add(v, ws[i == 0 ? 0 : (i <= 6 ? 1 : 2)]);
+      f[i] = x + ws[i == 0 ? 0 : (i <= 6 ? 1 : 2)];
     } else {
-      f[i] = Tr::decode(v);
+      f[i] = x;
     }
   }
+  return d;
 }
 
 template <Storage S, bool WALLS>
 __device__ __forceinline__ void pull(const __amdgpu_buffer_rsrc_t rz[3], uint32_t ppb, const Column& c,
-                                     uint32_t links, const float ws[2][3], float f[2][Q]) {
+                                     uint32_t links, const float ws[2][3], float f[2][Q], float d[2]) {
 #pragma unroll
-  for (int s = 0; s < 2; ++s) pull_species<S, WALLS>(rz, ppb, c, links, ws[s], s, f[s]);
-}
-
-__device__ __forceinline__ float sum19(const float f[Q]) {
-  float r = f[0];
-#pragma unroll
-  for (int i = 1; i < Q; ++i) r += f[i];
-  return r;
-}
-
-// ---------------------------------------------------------------------------
-// Cell-local algebra
-// ---------------------------------------------------------------------------
-
-// Pair k (0..8) holds directions 2k+1 (velocity p_k) and 2k+2 (-p_k):
-// p = (1,0,0) (0,1,0) (0,0,1) (1,1,0) (1,-1,0) (1,0,1) (1,0,-1) (0,1,1) (0,1,-1).
-__device__ __forceinline__ void pair_dots(float vx, float vy, float vz, float cv[9]) {
-  cv[0] = vx; cv[1] = vy; cv[2] = vz;
-  cv[3] = vx + vy; cv[4] = vx - vy;
-  cv[5] = vx + vz; cv[6] = vx - vz;
-  cv[7] = vy + vz; cv[8] = vy - vz;
-}
-
-__device__ __forceinline__ constexpr float pair_w(int k) { return k < 3 ? WF : WE; }
-
-// Everything a cell needs from its neighbourhood and its populations.
-struct Local {
-  float rho[2];  // rho^A, rho^B (Eq. 4)
-  float rinv;    // 1 / rho (Eq. 5)
-  float u[3];    // mixture velocity (Eq. 6)
-  float S[2][3]; // sum_i w_i c_i rho~^b(x + c_i) for b = A, B (Eq. 7)
-  float g[2][3]; // g^a = sum_b G^{ab} S^b (force per unit mass, Sec. 2)
-};
-
-// Mixture velocity of Eq. (6) from the pulled populations: u = j / rho.
-__device__ __forceinline__ void mixture_velocity(const float f[2][Q], float rho, float u[3]) {
-  float d[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) d[k] = (f[0][2 * k + 1] + f[1][2 * k + 1]) - (f[0][2 * k + 2] + f[1][2 * k + 2]);
-  const float rinv = 1.0f / rho;
-  u[0] = (d[0] + d[3] + d[4] + d[5] + d[6]) * rinv;
-  u[1] = (d[1] + d[3] - d[4] + d[7] + d[8]) * rinv;
-  u[2] = (d[2] + d[5] - d[6] + d[7] - d[8]) * rinv;
-}
-
-// Shan-Chen neighbour sum S^b(x) = sum_i w_i c_i rho~^b(x + c_i) (Eq. 7) from
-// the LDS density ring, in two parts.  `at` is the cell's position in a ring
-// plane (row stride EX).  shan_chen_partial takes the 13 neighbours in planes
-// z-1 (pm) and z (p0); shan_chen_finish adds the 5 in plane z+1 (pp).  Both
-// species at once (float2 = rho~^A, rho~^B).
-template <int EX>
-__device__ __forceinline__ void shan_chen_partial(const float2* pm, const float2* p0, int at, float2 S[3]) {
-  auto R = [&](const float2* pl, int dy, int dx) { return pl[at + dy * EX + dx]; };
-  const float2 a = R(p0, 0, 1), b = R(p0, 0, -1), c = R(p0, 1, 0), d = R(p0, -1, 0);
-  const float2 e = R(p0, 1, 1), f = R(p0, -1, 1), g = R(p0, 1, -1), h = R(p0, -1, -1);
-  const float2 m0 = R(pm, 0, 0), mx = R(pm, 0, 1), mxm = R(pm, 0, -1), my = R(pm, 1, 0), mym = R(pm, -1, 0);
-  // in plane: faces (w = 1/18) and xy edges (w = 1/36); plane below: c_z = -1
-  S[0].x = fmaf(WF, a.x - b.x, WE * (((e.x + f.x) - (g.x + h.x)) + (mx.x - mxm.x)));
-  S[0].y = fmaf(WF, a.y - b.y, WE * (((e.y + f.y) - (g.y + h.y)) + (mx.y - mxm.y)));
-  S[1].x = fmaf(WF, c.x - d.x, WE * (((e.x + g.x) - (f.x + h.x)) + (my.x - mym.x)));
-  S[1].y = fmaf(WF, c.y - d.y, WE * (((e.y + g.y) - (f.y + h.y)) + (my.y - mym.y)));
-  S[2].x = -fmaf(WF, m0.x, WE * ((mx.x + mxm.x) + (my.x + mym.x)));
-  S[2].y = -fmaf(WF, m0.y, WE * ((mx.y + mxm.y) + (my.y + mym.y)));
-}
-
-template <int EX>
-__device__ __forceinline__ void shan_chen_finish(const float2* pp, int at, float2 S[3]) {
-  auto R = [&](int dy, int dx) { return pp[at + dy * EX + dx]; };
-  const float2 p0 = R(0, 0), px = R(0, 1), pxm = R(0, -1), py = R(1, 0), pym = R(-1, 0);
-  S[0].x = fmaf(WE, px.x - pxm.x, S[0].x);
-  S[0].y = fmaf(WE, px.y - pxm.y, S[0].y);
-  S[1].x = fmaf(WE, py.x - pym.x, S[1].x);
-  S[1].y = fmaf(WE, py.y - pym.y, S[1].y);
-  S[2].x += fmaf(WF, p0.x, WE * ((px.x + pxm.x) + (py.x + pym.x)));
-  S[2].y += fmaf(WF, p0.y, WE * ((px.y + pxm.y) + (py.y + pym.y)));
-}
-
-__device__ __forceinline__ void make_local(const float rho_a, const float rho_b, const float u[3],
-                                           const float2 S[3], const Phys& ph, Local& L) {
-  L.rho[0] = rho_a;
-  L.rho[1] = rho_b;
-  L.rinv = 1.0f / (rho_a + rho_b);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    L.u[k] = u[k];
-    L.S[0][k] = S[k].x;
-    L.S[1][k] = S[k].y;
-    L.g[0][k] = ph.g_ab * S[k].y;  // g^A = G^{AB} S^B
-    L.g[1][k] = ph.g_ba * S[k].x;  // g^B = G^{BA} S^A
-  }
-}
-
-// BGK collision (Eq. 2) plus the exact-difference forcing term, in place:
-//   f*_i = (1 - w) f_i + w_i rho^a [(w - 1) P_i(u) + P_i(u + g^a)],  w = 1/tau_a,
-// with P the bracket of Eq. (3) at T0 = 1/3,
-//   P(v) = 1 + 3 cv + 4.5 cv^2 - 1.5 vv + 4.5 cv^3 - 4.5 cv vv,
-// evaluated per opposite pair as P(+-p_k) = even +- odd in cv.
-__device__ __forceinline__ float pair_dot(int k, float vx, float vy, float vz) {
-  switch (k) {
-    case 0: return vx;
-    case 1: return vy;
-    case 2: return vz;
-    case 3: return vx + vy;
-    case 4: return vx - vy;
-    case 5: return vx + vz;
-    case 6: return vx - vz;
-    case 7: return vy + vz;
-    default: return vy - vz;
-  }
-}
-
-__device__ __forceinline__ void collide(float f[2][Q], const Local& L, const Phys& ph) {
-  const float ux = L.u[0], uy = L.u[1], uz = L.u[2];
-  const float uu = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
-  const float au = fmaf(-1.5f, uu, 1.0f);
-  const float bu = fmaf(-4.5f, uu, 3.0f);
-  float vx[2], vy[2], vz[2], av[2], bv[2], om1[2], keep[2], r[2];
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    vx[s] = ux + L.g[s][0];
-    vy[s] = uy + L.g[s][1];
-    vz[s] = uz + L.g[s][2];
-    const float vv = fmaf(vx[s], vx[s], fmaf(vy[s], vy[s], vz[s] * vz[s]));
-    av[s] = fmaf(-1.5f, vv, 1.0f);
-    bv[s] = fmaf(-4.5f, vv, 3.0f);
-    om1[s] = ph.omega[s] - 1.0f;
-    keep[s] = 1.0f - ph.omega[s];
-    r[s] = L.rho[s];
-  }
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const float cu = pair_dot(k, ux, uy, uz);
-    const float tu = cu * cu;
-    const float eu = fmaf(4.5f, tu, au);
-    const float ou = cu * fmaf(4.5f, tu, bu);
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const float cv = pair_dot(k, vx[s], vy[s], vz[s]);
-      const float tv = cv * cv;
-      const float ke = fmaf(om1[s], eu, fmaf(4.5f, tv, av[s]));
-      const float ko = fmaf(om1[s], ou, cv * fmaf(4.5f, tv, bv[s]));
-      const float wr = pair_w(k) * r[s];
-      f[s][2 * k + 1] = fmaf(keep[s], f[s][2 * k + 1], wr * (ke + ko));
-      f[s][2 * k + 2] = fmaf(keep[s], f[s][2 * k + 2], wr * (ke - ko));
-    }
-  }
-  // Collision and forcing leave rho^a unchanged (sum_i w_i P_i(v) = 1).  The
-  // rest population is written as the remainder rho^a - sum_{i>0} f*_i, which
-  // equals (1 - w) f_0 + w_0 rho^a [(w - 1) P_0(u) + P_0(v^a)] in exact
-  // arithmetic; in FP32 it keeps the rounding of the weights 1/3, 1/18, 1/36
-  // (their FP32 values sum to 1 + 3e-8) from creating mass every step.
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    float moving = f[s][1];
-#pragma unroll
-    for (int i = 2; i < Q; ++i) moving += f[s][i];
-    f[s][0] = r[s] - moving;
-  }
-}
-
-// Regularized collision, Eqs. (10)-(11): f* = E(rho^a, u + g^a) +
-// (1 - w) w_i (c_i c_i - T0 I) : Pi^a / (2 T0^2), the second-order Hermite
-// projection of the non-equilibrium part, with
-// Pi^a = sum_i c_i c_i f_i - rho^a (T0 I + u u) (the second moment of Eq. 3
-// is exactly rho (T0 I + u u) on D3Q19).  The projection is even in c_i, so
-// both members of a pair get the same non-equilibrium part.  The rest
-// population is again the remainder rho^a - sum_{i>0} f*_i.
-__device__ __forceinline__ void collide_regularized(float f[2][Q], const Local& L, const Phys& ph) {
-  const float ux = L.u[0], uy = L.u[1], uz = L.u[2];
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const float r = L.rho[s];
-    float e[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) e[k] = f[s][2 * k + 1] + f[s][2 * k + 2];
-    const float rt = r * T0F;
-    const float pxx = (((e[0] + e[3]) + (e[4] + e[5])) + e[6]) - fmaf(r * ux, ux, rt);
-    const float pyy = (((e[1] + e[3]) + (e[4] + e[7])) + e[8]) - fmaf(r * uy, uy, rt);
-    const float pzz = (((e[2] + e[5]) + (e[6] + e[7])) + e[8]) - fmaf(r * uz, uz, rt);
-    const float pxy = (e[3] - e[4]) - (r * ux) * uy;
-    const float pxz = (e[5] - e[6]) - (r * ux) * uz;
-    const float pyz = (e[7] - e[8]) - (r * uy) * uz;
-    const float tt = T0F * ((pxx + pyy) + pzz);
-    float h[9];  // c . Pi . c - T0 tr(Pi) for pair k
-    h[0] = pxx - tt;
-    h[1] = pyy - tt;
-    h[2] = pzz - tt;
-    h[3] = fmaf(2.0f, pxy, pxx + pyy) - tt;
-    h[4] = fmaf(-2.0f, pxy, pxx + pyy) - tt;
-    h[5] = fmaf(2.0f, pxz, pxx + pzz) - tt;
-    h[6] = fmaf(-2.0f, pxz, pxx + pzz) - tt;
-    h[7] = fmaf(2.0f, pyz, pyy + pzz) - tt;
-    h[8] = fmaf(-2.0f, pyz, pyy + pzz) - tt;
-    const float vx = ux + L.g[s][0], vy = uy + L.g[s][1], vz = uz + L.g[s][2];
-    const float vv = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
-    const float av = fmaf(-1.5f, vv, 1.0f);
-    const float bv = fmaf(-4.5f, vv, 3.0f);
-    const float keep45 = 4.5f * (1.0f - ph.omega[s]);  // (1 - w) / (2 T0^2)
-    float moving = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const float cv = pair_dot(k, vx, vy, vz);
-      const float tv = cv * cv;
-      const float ev = fmaf(4.5f, tv, av);
-      const float ov = cv * fmaf(4.5f, tv, bv);
-      const float w = pair_w(k);
-      const float neq = w * (keep45 * h[k]);
-      f[s][2 * k + 1] = fmaf(w * r, ev + ov, neq);
-      f[s][2 * k + 2] = fmaf(w * r, ev - ov, neq);
-      moving += f[s][2 * k + 1] + f[s][2 * k + 2];
-    }
-    f[s][0] = r - moving;
-  }
+  for (int s = 0; s < 2; ++s) d[s] = pull_species<S, WALLS>(rz, ppb, c, links, ws[s], s, f[s]);
 }
 
 // Transposed collision of one cell (reverse mode of Eqs. 2-3 and 7).
@@ -502,15 +300,15 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
     const bool owner = ex < g.nx && ey < g.ny;  // ragged edge lanes only feed the ring
     const Column col = make_column<T>(ex, ey, g);
     const uint32_t col_b = col.y[1] + col.x[1];
-    const uint32_t col_off = col_b / static_cast<uint32_t>(sizeof(T));
+    const uint32_t col_off = col.cell;
     const int at = (ty + 1) * EX + tx + 1;
 
     float cur[2][Q], nxt[2][Q];
-    float cur_rho[2] = {0.f, 0.f}, nxt_rho[2] = {0.f, 0.f};
+    float cur_d[2] = {0.f, 0.f}, nxt_d[2] = {0.f, 0.f};  // stored sums D (pull_species)
     float cur_u[3] = {0.f, 0.f, 0.f}, nxt_u[3] = {0.f, 0.f, 0.f};
-    float2 cur_S[3], nxt_S[3];  // Shan-Chen sums from planes z-1 and z
+    float cur_S[2][3], nxt_S[2][3];  // Shan-Chen sums [species][axis] from planes z-1 and z
 #pragma unroll
-    for (int c = 0; c < 3; ++c) cur_S[c] = nxt_S[c] = make_float2(0.f, 0.f);
+    for (int c = 0; c < 3; ++c) cur_S[0][c] = cur_S[1][c] = nxt_S[0][c] = nxt_S[1][c] = 0.f;
     uint32_t cur_links = 0, nxt_links = 0;
     int slot = 0;  // k % 5
 
@@ -524,11 +322,11 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
       if constexpr (WALLS) nxt_links = io.links[static_cast<uint32_t>(zw) * g.nxy + col_off];
       const bool solid = WALLS && (nxt_links & 1u);
       if (!solid) {
-        pull<S, WALLS>(rz, ppb, col, nxt_links, ws, nxt);
-        nxt_rho[0] = sum19(nxt[0]);
-        nxt_rho[1] = sum19(nxt[1]);
-        ring[slot * PLANE + at] = make_float2(nxt_rho[0], nxt_rho[1]);
-        mixture_velocity(nxt, nxt_rho[0] + nxt_rho[1], nxt_u);
+        pull<S, WALLS>(rz, ppb, col, nxt_links, ws, nxt, nxt_d);
+        const float ra = density<S>(nxt_d[0], ph.shift[0]);
+        const float rb = density<S>(nxt_d[1], ph.shift[1]);
+        ring[slot * PLANE + at] = make_float2(ra, rb);
+        mixture_velocity(nxt, ra + rb, nxt_u);
       } else {
         ring[slot * PLANE + at] = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
       }
@@ -549,9 +347,10 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
           if (owner) {
             if constexpr (M == Mode::Step) {
               if (!csolid) {
-                shan_chen_finish<EX>(ring + slot * PLANE, at, cur_S);
+                shan_chen_finish<EX, 2>(ring + slot * PLANE, at, cur_S);
                 Local L;
-                make_local(cur_rho[0], cur_rho[1], cur_u, cur_S, ph, L);
+                make_local(density<S>(cur_d[0], ph.shift[0]), density<S>(cur_d[1], ph.shift[1]), cur_u, cur_S,
+                           ph, L);
                 if constexpr (REG) {
                   collide_regularized(cur, L, ph);
                 } else {
@@ -561,19 +360,9 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                   if constexpr (Tr::shifted) {
-                    // 16-bit storage: round the 18 moving populations, then
-                    // store the rest population so that the stored values
-                    // decode to a sum as close to rho^a as the format allows.
-                    float decoded = 0.0f;
-#pragma unroll
-                    for (int i = 1; i < Q; ++i) {
-                      const float w_s = ws[s][i <= 6 ? 1 : 2];
-                      const T q = Tr::sub_encode(cur[s][i], w_s);
-                      decoded += Tr::decode_add(q, w_s);
+                    encode_species<S>(cur[s], cur_d[s], ws[s], [&](int i, T q) {
                       buf_store<T>(q, rd, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
-                    }
-                    const T q0 = Tr::sub_encode(cur_rho[s] - decoded, ws[s][0]);
-                    buf_store<T>(q0, rd, col_b, static_cast<uint32_t>(s * Q) * ppb);
+                    });
                   } else {
 #pragma unroll
                     for (int i = 0; i < Q; ++i)
@@ -584,9 +373,10 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
             } else if constexpr (M == Mode::Moments) {
               float ra = 0.f, rb = 0.f, uf[3] = {0.f, 0.f, 0.f};
               if (!csolid) {
-                shan_chen_finish<EX>(ring + slot * PLANE, at, cur_S);
+                shan_chen_finish<EX, 2>(ring + slot * PLANE, at, cur_S);
                 Local L;
-                make_local(cur_rho[0], cur_rho[1], cur_u, cur_S, ph, L);
+                make_local(density<S>(cur_d[0], ph.shift[0]), density<S>(cur_d[1], ph.shift[1]), cur_u, cur_S,
+                           ph, L);
                 ra = L.rho[0];
                 rb = L.rho[1];
                 // u_F = u + g/2, g = sum_a rho^a g^a / rho  (Eqs. 8-9)
@@ -630,9 +420,10 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
               float mo[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
               float sb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
               if (!csolid) {
-                shan_chen_finish<EX>(ring + slot * PLANE, at, cur_S);
+                shan_chen_finish<EX, 2>(ring + slot * PLANE, at, cur_S);
                 Local L;
-                make_local(cur_rho[0], cur_rho[1], cur_u, cur_S, ph, L);
+                make_local(density<S>(cur_d[0], ph.shift[0]), density<S>(cur_d[1], ph.shift[1]), cur_u, cur_S,
+                           ph, L);
                 // One species at a time: lam^a = dL/dX at the cell, and the
                 // populations of plane z, pulled again (cache hits) rather
                 // than held in registers since they were first read.
@@ -668,7 +459,7 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
           }
         }
         // Planes p_{k-1} and p_k are complete: the first part of S for plane p_k.
-        if (k < kmax) shan_chen_partial<EX>(ring + sm1 * PLANE, ring + slot * PLANE, at, nxt_S);
+        if (k < kmax) shan_chen_partial<EX, 2>(ring + sm1 * PLANE, ring + slot * PLANE, at, nxt_S);
       }
 
 #pragma unroll
@@ -677,12 +468,13 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
 #pragma unroll
           for (int i = 0; i < Q; ++i) cur[s][i] = nxt[s][i];
         }
-        cur_rho[s] = nxt_rho[s];
+        cur_d[s] = nxt_d[s];
       }
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         cur_u[c] = nxt_u[c];
-        cur_S[c] = nxt_S[c];
+        cur_S[0][c] = nxt_S[0][c];
+        cur_S[1][c] = nxt_S[1][c];
       }
       cur_links = nxt_links;
       slot = slot == 4 ? 0 : slot + 1;
@@ -702,7 +494,7 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
       int hx = 0, hy = 0;
       halo_pos<BXT, ROWS>(has[j] ? h : 0, hx, hy);
       hcol[j] = make_column<T>(x0 + hx, y0 + hy, g);
-      hcol_off[j] = (hcol[j].y[1] + hcol[j].x[1]) / static_cast<uint32_t>(sizeof(T));
+      hcol_off[j] = hcol[j].cell;
       hat[j] = (hy + 1) * EX + hx + 1;
     }
 
@@ -723,9 +515,9 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
         if (WALLS && (lk & 1u)) {
           r = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
         } else {
-          float hf[2][Q];
-          pull<S, WALLS>(rz, ppb, hcol[j], lk, ws, hf);
-          r = make_float2(sum19(hf[0]), sum19(hf[1]));
+          float hf[2][Q], hd[2];
+          pull<S, WALLS>(rz, ppb, hcol[j], lk, ws, hf, hd);
+          r = make_float2(density<S>(hd[0], ph.shift[0]), density<S>(hd[1], ph.shift[1]));
         }
         ring[sl * PLANE + hat[j]] = r;
       }
@@ -753,11 +545,14 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
 // Launch
 // ---------------------------------------------------------------------------
 
-// Tile shapes selectable at run time: (columns, rows, halo waves).
+// Tile shapes selectable at run time: (columns of cells, rows, halo waves);
+// shapes 6..9 are the paired march over folded 16-bit rows (2 cells per lane).
 struct TileShape {
   int bx, rows, hw;
 };
-constexpr TileShape TILES[] = {{64, 8, 3}, {64, 12, 3}, {32, 16, 2}, {128, 4, 3}, {64, 4, 3}, {256, 2, 3}};
+constexpr TileShape TILES[] = {{64, 8, 3},  {64, 12, 3}, {32, 16, 2}, {128, 4, 3}, {64, 4, 3},
+                               {256, 2, 3}, {128, 8, 3}, {64, 16, 2}, {64, 8, 2},  {64, 12, 2}};
+static_assert(sizeof(TILES) / sizeof(TILES[0]) == TILE_SHAPES, "one entry per tile shape");
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
 
 Tiling make_tiling(const Grid& g, int tile, int zchunk) {
@@ -799,14 +594,17 @@ Tiling make_tiling(const Grid& g, int tile, int zchunk) {
 int auto_tile(const Grid& g, bool walls, int elem_bytes) {
   // FP32 without walls: widest rows first (128-lane rows read whole 512-byte
   // population rows).  With walls (the 128 x 4 shape keeps too few registers
-  // for the wall path) and for 16-bit storage (measured faster) 64 x 8 comes
-  // first.  A later shape wins only by padding the x-y plane less (lanes past
-  // nx or ny do no work).
+  // for the wall path) and for unfolded 16-bit rows (measured faster) 64 x 8
+  // comes first.  Folded 16-bit rows without walls take the paired march.
+  // A later shape wins only by padding the x-y plane less (lanes past nx or
+  // ny do no work).
   static constexpr int open_order[] = {3, 0, 2};
   static constexpr int tall_order[] = {0, 2};
+  static constexpr int pair_order[] = {8, 9};
+  const bool paired = elem_bytes == 2 && g.half != 0 && !walls;
   const bool tall = walls || elem_bytes != 4;
-  const int* order = tall ? tall_order : open_order;
-  const int count = tall ? 2 : 3;
+  const int* order = paired ? pair_order : (tall ? tall_order : open_order);
+  const int count = paired ? 2 : (tall ? 2 : 3);
   int best = order[0];
   long long best_cells = -1;
   for (int k = 0; k < count; ++k) {
@@ -883,6 +681,10 @@ static hipError_t launch_mode(Mode mode, const Grid& g, const Phys& ph, const Ti
 hipError_t launch_march(Storage s, Mode mode, const Grid& g, const Phys& ph, const Tiling& t,
                         const MarchIO& io, hipStream_t st) {
   if (t.blocks <= 0) return hipErrorInvalidValue;
+  if (pair_shape(t.tile)) {
+    if (mode != Mode::Step) return hipErrorInvalidValue;
+    return launch_pair_step(s, g, ph, t, io, st);
+  }
   if (mode == Mode::Adjoint) {
     if (s != Storage::F32) return hipErrorInvalidValue;
     return launch_walls<Storage::F32, Mode::Adjoint>(g, ph, t, io, st);

@@ -40,7 +40,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SOURCES = ("march.hip", "buffer.h", "lattice.h", "launch.h")
+KERNEL_SOURCES = ("march.hip", "march_pair.hip", "cell.h", "buffer.h", "lattice.h", "launch.h")
 BYTES_PER_CELL = {"fp32": 304, "fp16": 152, "bf16": 152}
 SHAPES = {"128": (128, 128, 128), "512": (512, 512, 512), "walls": (192, 192, 384)}
 
@@ -143,7 +143,8 @@ def _is_copy(name):
 
 
 def _is_step(name):
-    return "march_kernel" in name and "(lbm::Mode)0" in name
+    # single-cell march in Step mode, or the paired march (Step only)
+    return ("march_kernel" in name and "(lbm::Mode)0" in name) or "march_pair_kernel" in name
 
 
 def cmd_traffic(args):

@@ -93,10 +93,15 @@ class Sim:
         self.state_elems = int(self.lib.lbm_state_elems(nx, ny, nz, code))
         self.lam_pstride = int(self.lib.lbm_plane_stride(nx, ny, _lib.FP32))
         self.lam_elems = int(self.lib.lbm_state_elems(nx, ny, nz, _lib.FP32))
-        if min(self.pstride, self.state_elems, self.lam_elems) < 0:
+        self.row_half = int(self.lib.lbm_row_half(nx, code, int(solid is not None)))
+        if min(self.pstride, self.state_elems, self.lam_elems, self.row_half) < 0:
             raise ValueError(f"grid {self.shape} is not supported")
 
         with torch.cuda.device(self.device):
+            # Row position of cell x in the stored state (folded 16-bit rows, lbm.h).
+            x = torch.arange(nx, device=self.device)
+            h = self.row_half
+            self.x_pos = torch.where(x < h, 2 * x, 2 * (x - h) + 1) if h else x
             self.stream = torch.cuda.current_stream(self.device)
             # zeroed so that the padding between planes holds defined values
             self.bufs = [torch.zeros(self.state_elems, dtype=self.dtype, device=self.device) for _ in range(2)]
@@ -145,10 +150,15 @@ class Sim:
         return self.bufs[self.t & 1]
 
     def plane_view(self, flat, pstride=None):
-        """(nz, 2, 19, ny, nx) view of a flat plane-major buffer (state layout)."""
+        """(nz, 2, 19, ny, nx) view of a flat plane-major buffer in stored row
+        order: the last index is the row position (see :attr:`x_pos`)."""
         nz, ny, nx = self.shape
         ps = self.pstride if pstride is None else pstride
         return flat.view(nz, 2, Q, ps)[..., : nx * ny].unflatten(-1, (ny, nx))
+
+    def _row_order(self, flat):
+        # the stored state is folded for 16-bit rows; adjoint arrays (FP32) never are
+        return self.row_half and flat.dtype != torch.float32
 
     def to_state_layout(self, f, pstride=None, elems=None):
         """(2, 19, nz, ny, nx) array -> new flat plane-major buffer (zero padding)."""
@@ -156,12 +166,19 @@ class Sim:
         ps = self.pstride if pstride is None else pstride
         n = self.state_elems if elems is None else elems
         out = torch.zeros(n, dtype=f.dtype, device=f.device)
-        self.plane_view(out, ps).copy_(f.reshape(2, Q, nz, ny, nx).permute(2, 0, 1, 3, 4))
+        src = f.reshape(2, Q, nz, ny, nx).permute(2, 0, 1, 3, 4)
+        if self._row_order(out):
+            self.plane_view(out, ps)[..., self.x_pos.to(f.device)] = src
+        else:
+            self.plane_view(out, ps).copy_(src)
         return out
 
     def from_state_layout(self, flat, pstride=None):
-        """Flat plane-major buffer -> (2, 19, nz, ny, nx) contiguous copy."""
-        return self.plane_view(flat, pstride).permute(1, 2, 0, 3, 4).contiguous()
+        """Flat plane-major buffer -> (2, 19, nz, ny, nx) contiguous copy (cell order)."""
+        v = self.plane_view(flat, pstride)
+        if self._row_order(flat):
+            v = v[..., self.x_pos.to(flat.device)]
+        return v.permute(1, 2, 0, 3, 4).contiguous()
 
     # -- observables -------------------------------------------------------------
     def moments(self, region=None, want_fields=True):

@@ -112,6 +112,18 @@ def test_plane_stride_and_state_size(lib):
     assert lib.lbm_state_elems(4, 4, 0, _lib.FP32) == -1
 
 
+def test_row_fold_query(lib):
+    """16-bit rows of even length without walls are folded (h = nx/2); FP32
+    rows, odd nx and contexts with walls are not."""
+    from paper_1601_01237_amd import _lib
+    for nx, st, walls, want in [(64, _lib.FP16, 0, 32), (70, _lib.BF16, 0, 35), (2, _lib.FP16, 0, 1),
+                                (7, _lib.FP16, 0, 0), (64, _lib.FP32, 0, 0), (1, _lib.BF16, 0, 0),
+                                (64, _lib.FP16, 1, 0), (70, _lib.BF16, 1, 0)]:
+        assert lib.lbm_row_half(nx, st, walls) == want, (nx, st, walls)
+    assert lib.lbm_row_half(0, _lib.FP16, 0) == -1
+    assert lib.lbm_row_half(8, 3, 0) == -1
+
+
 def _valid_params(_lib):
     p = _lib.Params()
     p.nx, p.ny, p.nz = 8, 8, 8

@@ -59,7 +59,7 @@ def _patches(sim, centers):
     c = torch.as_tensor(centers, device=st.device)
     zi = (c[:, 0, None] + d[None, :]) % nz
     yi = (c[:, 1, None] + d[None, :]) % ny
-    xi = (c[:, 2, None] + d[None, :]) % nx
+    xi = sim.x_pos[(c[:, 2, None] + d[None, :]) % nx]  # row positions (folded 16-bit rows)
     zz = zi[:, :, None, None].expand(-1, 5, 5, 5)
     yy = yi[:, None, :, None].expand(-1, 5, 5, 5)
     xx = xi[:, None, None, :].expand(-1, 5, 5, 5)
