@@ -216,8 +216,8 @@ lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
  * 1 = 64x12, 2 = 32x16, 3 = 128x4, 4 = 64x4, 5 = 256x2.  Shapes with one
  * folded 32-bit word (two cells) per lane, for 16-bit storage with folded
  * rows and no walls only (else LBM_EINVAL), in words by rows: 6 = 64x8,
- * 7 = 32x16, 8 = 32x8, 9 = 32x12.  -1 (the default) picks, among 8 and 9 for
- * folded 16-bit rows without walls, else among 128x4, 64x8 and 32x16 (64x8
+ * 7 = 32x16, 8 = 32x8, 9 = 32x12.  -1 (the default) picks 8 for folded
+ * 16-bit rows without walls, else among 128x4, 64x8 and 32x16 (64x8
  * and 32x16 with walls or 16-bit storage), the one that pads the x-y plane
  * least, the first listed on a tie.  Results do not depend on this choice
  * (bitwise).

@@ -595,16 +595,18 @@ int auto_tile(const Grid& g, bool walls, int elem_bytes) {
   // FP32 without walls: widest rows first (128-lane rows read whole 512-byte
   // population rows).  With walls (the 128 x 4 shape keeps too few registers
   // for the wall path) and for unfolded 16-bit rows (measured faster) 64 x 8
-  // comes first.  Folded 16-bit rows without walls take the paired march.
+  // comes first.  Folded 16-bit rows without walls take the paired march in
+  // 32 x 8 words (measured fastest of the pair shapes at 512^3: one 128-byte
+  // line per population row and six waves per CU).
   // A later shape wins only by padding the x-y plane less (lanes past nx or
   // ny do no work).
   static constexpr int open_order[] = {3, 0, 2};
   static constexpr int tall_order[] = {0, 2};
-  static constexpr int pair_order[] = {8, 9};
+  static constexpr int pair_order[] = {8};
   const bool paired = elem_bytes == 2 && g.half != 0 && !walls;
   const bool tall = walls || elem_bytes != 4;
   const int* order = paired ? pair_order : (tall ? tall_order : open_order);
-  const int count = paired ? 2 : (tall ? 2 : 3);
+  const int count = paired ? 1 : (tall ? 2 : 3);
   int best = order[0];
   long long best_cells = -1;
   for (int k = 0; k < count; ++k) {

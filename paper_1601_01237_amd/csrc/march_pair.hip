@@ -61,7 +61,9 @@ __device__ __forceinline__ PairColumn make_pair_column(int d, int ey, const Grid
 
 __device__ __forceinline__ uint32_t trade_halves(uint32_t w) { return __builtin_amdgcn_alignbit(w, w, 16); }
 
-// Pull (Eq. 1) of the 19 words of species s for the two cells of column c.
+// Pull (Eq. 1) of the 19 words of species s for the two cells of column c:
+// the loads, then (fold_fix, once the words are in) the trade of halves for
+// the sources across the fold.
 template <Storage S>
 __device__ __forceinline__ void pull_words(const __amdgpu_buffer_rsrc_t rz[3], uint32_t ppb, const PairColumn& c,
                                            int s, uint32_t w[Q]) {
@@ -70,15 +72,24 @@ __device__ __forceinline__ void pull_words(const __amdgpu_buffer_rsrc_t rz[3], u
     const uint32_t off = c.y[1 - CY[i]] + c.x[1 - CX[i]];
     w[i] = __builtin_amdgcn_raw_buffer_load_b32(rz[1 - CZ[i]], off, static_cast<uint32_t>(s * Q + i) * ppb, 0);
   }
+}
+
+__device__ __forceinline__ void fold_fix(const PairColumn& c, uint32_t w[2][Q]) {
   if (c.swap_p) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-      if (CX[i] == 1) w[i] = trade_halves(w[i]);
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        if (CX[i] == 1) w[s][i] = trade_halves(w[s][i]);
+    }
   }
   if (c.swap_m) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-      if (CX[i] == -1) w[i] = trade_halves(w[i]);
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        if (CX[i] == -1) w[s][i] = trade_halves(w[s][i]);
+    }
   }
 }
 
@@ -182,18 +193,28 @@ march_pair_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io
     const uint32_t col_b = col.y[1] + col.x[1];
     const int at = (ty + 1) * EX + tx + 1;
 
-    uint32_t cur[2][Q], nxt[2][Q];
+    // Words of three planes: cur = p_{k-1} (collided after barrier k),
+    // nxt = p_k (its densities go into the ring before barrier k) and ahead =
+    // p_{k+1}, loaded one iteration early so that its latency overlaps the
+    // barrier and the collision of p_{k-1}.
+    uint32_t cur[2][Q], nxt[2][Q], ahead[2][Q];
     float cur_d[2][2] = {{0.f, 0.f}, {0.f, 0.f}}, nxt_d[2][2];  // stored sums [cell][species]
     int slot = 0;  // k % 5
-
-    for (int k = 0; k <= kmax; ++k) {
+    auto load_plane = [&](int k, uint32_t w[2][Q]) {
       const int p = z0 - 1 + k;
       __amdgpu_buffer_rsrc_t rz[3];
       rz[0] = plane_rsrc<T>(io.src, wrap(p - 1, g.nz), g);
       rz[1] = plane_rsrc<T>(io.src, wrap(p, g.nz), g);
       rz[2] = plane_rsrc<T>(io.src, wrap(p + 1, g.nz), g);
-      pull_words<S>(rz, ppb, col, 0, nxt[0]);
-      pull_words<S>(rz, ppb, col, 1, nxt[1]);
+      pull_words<S>(rz, ppb, col, 0, w[0]);
+      pull_words<S>(rz, ppb, col, 1, w[1]);
+    };
+    load_plane(0, nxt);
+
+    for (int k = 0; k <= kmax; ++k) {
+      const int p = z0 - 1 + k;
+      if (k < kmax) load_plane(k + 1, ahead);
+      fold_fix(col, nxt);
       ring[slot * PLANE + at] = ring_entry<S>(nxt, ph, col.flip, nxt_d);
 
       if (k >= 1) {
@@ -244,7 +265,10 @@ march_pair_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) cur[s][i] = nxt[s][i];
+        for (int i = 0; i < Q; ++i) {
+          cur[s][i] = nxt[s][i];
+          nxt[s][i] = ahead[s][i];
+        }
         cur_d[0][s] = nxt_d[0][s];
         cur_d[1][s] = nxt_d[1][s];
       }
@@ -280,6 +304,7 @@ march_pair_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io
         float hd[2][2];
         pull_words<S>(rz, ppb, hcol[j], 0, w[0]);
         pull_words<S>(rz, ppb, hcol[j], 1, w[1]);
+        fold_fix(hcol[j], w);
         ring[sl * PLANE + hat[j]] = ring_entry<S>(w, ph, hcol[j].flip, hd);
       }
     };
