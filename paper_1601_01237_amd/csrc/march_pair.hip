@@ -309,6 +309,10 @@ march_pair_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io
       }
     };
 
+    // Planes p_0 .. p_2 before the first barrier, then p_{k+2} after barrier
+    // k.  (The single-cell march fills p_{k+1} there, in step with its own
+    // pulls; with the own loads prefetched here, that put the halo loads on
+    // the critical path: 6.3 against 4.7 ms at 512^3.)
     for (int k = 0; k <= min(2, kmax); ++k) halo_plane(k);
     for (int k = 1; k <= kmax; ++k) {
       __syncthreads();
