@@ -6,7 +6,8 @@ marches run the same cell arithmetic, so their stored states must agree
 bitwise over several steps, tile shapes and z chunks; the single-cell march
 and the paired one are each checked against the oracle elsewhere (odd and
 even nx).  Shapes cover a ragged x-y plane, the shortest folded row (nx = 2,
-where both fold crossings hit the same word) and rows longer than one tile.
+where both fold crossings hit the same word), rows longer than one tile, and
+one- and two-plane boxes (every z neighbour is the plane itself or the other).
 """
 
 import numpy as np
@@ -20,7 +21,7 @@ from ._gpu_util import oracle_run, rel_err, say
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(20, 19, 70), (6, 5, 2), (9, 7, 130), (5, 33, 64)]
+SHAPES = [(20, 19, 70), (6, 5, 2), (9, 7, 130), (5, 33, 64), (1, 1, 2), (2, 1, 6), (1, 3, 4)]
 PAIR_TILINGS = [(6, 0), (7, 0), (8, 0), (9, 0), (6, 1), (7, 3), (8, 2), (9, 5)]
 
 
