@@ -143,6 +143,39 @@ def copy_ceiling(gib=4.0, reps=10):
     return 2.0 * n / (ms * 1e-3) / 1e9
 
 
+def pattern_ceiling(shape, storage="fp32", reps=20):
+    """Rate (GB/s of algorithmic bytes) of lbm_march_copy on ``shape``: the
+    step's access pattern (tiles, z march, 38 loads then 38 stores per cell)
+    with no arithmetic, halo or re-read."""
+    import torch
+    from paper_1601_01237_amd import inputs
+    from paper_1601_01237_amd.sim import Sim
+    sim = Sim(inputs.sphere_droplet(shape, radius=4.0, seed=0), storage=storage)
+    src = sim.bufs[0]
+    dst = torch.empty_like(sim.bufs[1])
+    for _ in range(2):
+        _lib_call(sim, src, dst)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(sim.stream)
+    for _ in range(reps):
+        _lib_call(sim, src, dst)
+    end.record(sim.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / reps
+    n = int(np.prod(shape))
+    sim.close()
+    del dst
+    return BYTES_PER_CELL[storage] * n / (ms * 1e-3) / 1e9
+
+
+def _lib_call(sim, src, dst):
+    import ctypes
+    from paper_1601_01237_amd import _lib
+    _lib.check("lbm_march_copy", sim.lib.lbm_march_copy(sim.ctx, ctypes.c_void_p(src.data_ptr()),
+                                                         ctypes.c_void_p(dst.data_ptr())))
+
+
 def cpu_baseline(shape, seconds_budget=12.0, max_steps=8):
     """The FP64 oracle on whole steps of the headline workload, one thread.
 
@@ -205,6 +238,7 @@ def main():
     extra = {}
     print("[bench] copy ceiling", file=sys.stderr, flush=True)
     ceiling = copy_ceiling()
+    pattern = pattern_ceiling(shape)
     if not args.no_extra:
         steps_big = max(10, args.steps // 10)
         big = (512, 512, 512)
@@ -254,6 +288,8 @@ def main():
                      "algorithmic_bytes_per_cell": BYTES_PER_CELL["fp32"],
                      "copy_ceiling_gbs": round(ceiling, 1),
                      "frac_of_copy_ceiling": round(achieved / ceiling, 4),
+                     "pattern_ceiling_gbs": round(pattern, 1),
+                     "frac_of_pattern_ceiling": round(achieved / pattern, 4),
                      "kernel": "march_kernel<F32, no walls, Step, 128x4 tile>"},
         "cpu_baseline": cpu,
         "extra": extra,

@@ -259,6 +259,15 @@ lbm_status lbm_adjoint_seed(lbm_ctx *ctx, const float *grad_rho, float *lam);
  * the step kernel's bandwidth is compared. */
 lbm_status lbm_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
 
+/* Copies the nx*ny cells of every population plane of a stored state `src`
+ * to `dst` (device, lbm_state_elems(nx, ny, nz, storage) elements each,
+ * distinct; padding not written) with the memory pattern of the step: one
+ * workgroup per 128 x 4 column tile marching its chunk of z planes, 38 loads
+ * then 38 stores per cell and plane, on the context's stream.  Not part of
+ * the method: it moves exactly the step's algorithmic bytes with no
+ * arithmetic, so its rate is the ceiling of the step's access pattern. */
+lbm_status lbm_march_copy(lbm_ctx *ctx, const void *src, void *dst);
+
 /* Frees the context and what the library allocated; NULL is a no-op.
  * Waits for the context's stream first. */
 lbm_status lbm_destroy(lbm_ctx *ctx);

@@ -69,6 +69,7 @@ def _declare(lib):
         "lbm_adjoint_step": (i32, [vp, vp, vp, vp, vp, C.c_size_t, vp, vp]),
         "lbm_adjoint_seed": (i32, [vp, vp, vp]),
         "lbm_stream_copy": (i32, [vp, vp, C.c_size_t, vp]),
+        "lbm_march_copy": (i32, [vp, vp, vp]),
         "lbm_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -99,7 +100,7 @@ EXPORTED = ["lbm_version", "lbm_velocity_set", "lbm_status_str", "lbm_plane_stri
             "lbm_state_elems", "lbm_row_half", "lbm_init", "lbm_step",
             "lbm_moments", "lbm_get_populations", "lbm_set_populations", "lbm_time",
             "lbm_set_time", "lbm_set_tiling", "lbm_adjoint_work_bytes", "lbm_adjoint_step",
-            "lbm_adjoint_seed", "lbm_stream_copy", "lbm_destroy"]
+            "lbm_adjoint_seed", "lbm_stream_copy", "lbm_march_copy", "lbm_destroy"]
 
 
 def velocity_set():

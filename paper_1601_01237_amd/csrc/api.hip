@@ -320,6 +320,11 @@ lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, void* strea
   return from_hip(launch_stream_copy(src, dst, bytes, static_cast<hipStream_t>(stream)));
 }
 
+lbm_status lbm_march_copy(lbm_ctx* c, const void* src, void* dst) {
+  if (!c || !src || !dst || src == dst) return LBM_EINVAL;
+  return from_hip(launch_march_copy(c->storage, c->g, src, dst, c->stream));
+}
+
 lbm_status lbm_destroy(lbm_ctx* c) {
   if (!c) return LBM_OK;
   const hipError_t e = hipStreamSynchronize(c->stream);

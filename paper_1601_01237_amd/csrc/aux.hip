@@ -180,6 +180,36 @@ __global__ void __launch_bounds__(256) stream_copy_kernel(const u32x4* __restric
   if (i < n16) __builtin_nontemporal_store(src[i], &dst[i]);
 }
 
+// The fused step's memory pattern without its arithmetic: one workgroup per
+// 128 x 4 column tile marches its chunk of z planes (the step's automatic
+// tiling for FP32), and per plane every lane loads the 38 population values
+// of its cell, then stores them (non-temporal) at the same place in dst.  No
+// halo and no re-read: it moves exactly the step's algorithmic bytes, so its
+// rate is the ceiling of that access pattern on the device.
+template <typename T>
+__global__ void __launch_bounds__(512) march_copy_kernel(const Grid g, const Tiling tl, const T* __restrict__ src,
+                                                         T* __restrict__ dst) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int tiles_xy = tl.tiles_x * tl.tiles_y;
+  const int bz = b / tiles_xy;
+  const int rem = b - bz * tiles_xy;
+  const int byy = rem / tl.tiles_x;
+  const int bxx = rem - byy * tl.tiles_x;
+  const int x = bxx * 128 + static_cast<int>(threadIdx.x & 127u);
+  const int y = byy * 4 + static_cast<int>(threadIdx.x >> 7);
+  if (x >= g.nx || y >= g.ny) return;  // no barriers below
+  const uint64_t col = static_cast<uint64_t>(y) * g.nx + x;
+  const int z1 = min((bz + 1) * tl.zchunk, g.nz);
+  for (int z = bz * tl.zchunk; z < z1; ++z) {
+    const uint64_t base = static_cast<uint64_t>(z) * 2 * Q * g.pstride + col;
+    T v[2 * Q];
+#pragma unroll
+    for (int i = 0; i < 2 * Q; ++i) v[i] = src[base + static_cast<uint64_t>(i) * g.pstride];
+#pragma unroll
+    for (int i = 0; i < 2 * Q; ++i) __builtin_nontemporal_store(v[i], &dst[base + static_cast<uint64_t>(i) * g.pstride]);
+  }
+}
+
 unsigned grid_for(uint64_t n) {
   uint64_t b = (n + TPB - 1) / TPB;
   if (b > 65536ull * 16) b = 65536ull * 16;
@@ -261,6 +291,19 @@ hipError_t launch_finalize(const double* partials, int blocks, int nvals, const 
       if (is_max[k]) max_index = k;
   hipLaunchKernelGGL(finalize_kernel, dim3(nvals), dim3(TPB), 0, st, partials, blocks, nvals,
                      static_cast<const int*>(nullptr), max_index, out, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_march_copy(Storage s, const Grid& g, const void* src, void* dst, hipStream_t st) {
+  const Tiling t = make_tiling(g, 3, 0);  // 128 x 4 tiles, the default chunk of z planes
+  if (t.blocks <= 0) return hipErrorInvalidValue;
+  if (s == Storage::F32) {
+    hipLaunchKernelGGL(march_copy_kernel<float>, dim3(t.blocks), dim3(512), 0, st, g, t,
+                       static_cast<const float*>(src), static_cast<float*>(dst));
+  } else {
+    hipLaunchKernelGGL(march_copy_kernel<uint16_t>, dim3(t.blocks), dim3(512), 0, st, g, t,
+                       static_cast<const uint16_t*>(src), static_cast<uint16_t*>(dst));
+  }
   return hipGetLastError();
 }
 

@@ -93,6 +93,7 @@ hipError_t launch_adjoint_stream(const Grid& g, const Phys& ph, const uint32_t* 
                                  const float* lam_in, const float* m, float* lam_out,
                                  double* drho0, hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStream_t st);
+hipError_t launch_march_copy(Storage s, const Grid& g, const void* src, void* dst, hipStream_t st);
 hipError_t launch_adjoint_seed(const Grid& g, const uint32_t* links, const float* grad_rho,
                                float* lam, hipStream_t st);
 

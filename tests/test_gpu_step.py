@@ -201,3 +201,26 @@ def test_checkpoint_resume_bitwise(lib):
     assert s.t == 20
     assert torch.equal(s.state, ref)
     s.close()
+
+
+@pytest.mark.parametrize("storage,shape", [("fp32", (5, 9, 130)), ("fp16", (3, 7, 70)), ("fp32", (17, 4, 128))])
+def test_march_copy_reference(lib, storage, shape):
+    """lbm_march_copy (the bandwidth reference with the step's access
+    pattern) copies every cell of every population plane and nothing else."""
+    import ctypes
+    import torch
+    from paper_1601_01237_amd.sim import Sim
+    say(f"march copy {storage} {shape}")
+    sim = Sim(inputs.sphere_droplet(shape, radius=2.0, seed=1), storage=storage)
+    sim.step(2)
+    src = sim.state
+    dst = torch.full_like(src, 7.0)
+    code = sim.lib.lbm_march_copy(sim.ctx, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()))
+    assert code == 0
+    torch.cuda.synchronize()
+    assert torch.equal(sim.plane_view(dst), sim.plane_view(src))
+    nz, ny, nx = shape
+    pad = dst.view(nz, 2, 19, sim.pstride)[..., nx * ny:]
+    assert bool((pad == 7.0).all())  # padding untouched
+    assert sim.lib.lbm_march_copy(sim.ctx, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(src.data_ptr())) != 0
+    sim.close()
