@@ -5,8 +5,8 @@
 // its cells (Eq. 1 in pull form, with halfway bounce-back at walls, Sec. 4)
 // and reduces the species densities rho^A, rho^B (Eq. 4) into a 5-slot LDS
 // ring that also holds a one-cell halo of the tile.  Separate halo waves
-// recompute the halo densities from the populations around the tile, one
-// plane ahead of the owner waves, so no density field ever travels through
+// recompute the halo densities from the populations around the tile, in
+// step with the owner waves' pulls, so no density field ever travels through
 // HBM.  Once plane z+1 is in the ring, plane z has every neighbour density the
 // Shan-Chen sum of Eq. (7) needs, and the cell update (Eqs. 2-9) runs from the
 // populations the owner thread kept in registers.
@@ -16,8 +16,9 @@
 //   Moments  rho^a and u_F fields plus FP64 per-workgroup diagnostic sums;
 //   Adjoint  per-cell transposed collision (see below) for one reverse step.
 //
-// Memory layout: plane-major X[z][a][i][y][x], x fastest, so each population
-// load of a 64-wide row is one contiguous 256-byte run (FP32) and one z plane
+// Memory layout: plane-major X[z][a][i][y][pos(x)] (pos(x) = x except on
+// folded 16-bit rows, see buffer.h), so each population load of a 64-wide
+// row is one contiguous 256-byte run (FP32) and one z plane
 // of all 38 populations is one contiguous block; population planes are padded
 // (Grid::pstride) so that they are not a power of two apart.  Blocks are remapped
 // so that the tiles dispatched to one XCD (block id mod 8) are contiguous in
