@@ -17,6 +17,7 @@ Q = 19
 DIAG_LEN = 16
 FP32, FP16, BF16 = 0, 1, 2
 BGK, REGULARIZED = 0, 1
+EUNSTABLE = -4
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "HIP runtime error", -3: "invalid state",
           -4: "non-finite values (unstable run)", -5: "not supported"}

@@ -140,6 +140,30 @@ class Sim:
     def step(self, n=1):
         _lib.check("lbm_step", self.lib.lbm_step(self.ctx, int(n)))
 
+    def run(self, n, check_every=0):
+        """Advance n steps.  With check_every > 0, read the diagnostics every
+        check_every steps and after the last one, and raise LBMError with
+        code LBM_EUNSTABLE (-4) at the first time level that holds a
+        non-finite density or velocity; the state of that time level is kept
+        (restore a checkpoint to recover)."""
+        n = int(n)
+        if check_every <= 0:
+            self.step(n)
+            return
+        done = 0
+        while done < n:
+            k = min(int(check_every), n - done)
+            self.step(k)
+            done += k
+            self.check_finite()
+
+    def check_finite(self):
+        """Raise LBMError(LBM_EUNSTABLE) if the current state holds a
+        non-finite density or velocity on any fluid cell."""
+        _, _, d = self.moments(want_fields=False)
+        if d["nonfinite"] > 0:
+            raise _lib.LBMError(f"lbm_step (t = {self.t}, {int(d['nonfinite'])} cells)", _lib.EUNSTABLE)
+
     def set_tiling(self, tile=-1, zchunk=0):
         """Tile shape of the step kernel (-1 = automatic, 0..5, see lbm_set_tiling) and z planes per workgroup."""
         _lib.check("lbm_set_tiling", self.lib.lbm_set_tiling(self.ctx, int(tile), int(zchunk)))

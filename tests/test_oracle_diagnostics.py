@@ -39,3 +39,24 @@ def test_centre_of_mass_follows_a_shift_across_the_periodic_boundary():
     d = D.diagnostics(f, p, center=(10.0, 6.0, 6.0))
     # droplet centred at x = 11 seen from x = 10 across the wrap: mean offset +1
     assert abs(d[D.SDX_THR] / d[D.N_THR] - 1.0) < 1e-12
+
+
+def test_divergent_run_is_flagged():
+    """tau just above 1/2 with a strongly supercritical coupling diverges; the
+    non-finite count of the diagnostics (what the GPU wrapper checks) flags
+    it within a few tens of steps, and a stable run never does."""
+    import warnings
+    shape = (12, 12, 12)
+    rho0 = inputs.sphere_droplet(shape, radius=4.0, seed=0)
+    for tau, G, diverges in ((0.51, -3.0, True), (1.0, -1.0, False)):
+        p = lbm.Params(tau=(tau, tau), G=((0.0, G), (G, 0.0)))
+        f = lbm.init_state(rho0)
+        flagged = None
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", RuntimeWarning)
+            for t in range(1, 41):
+                f = lbm.step(f, p)
+                if D.diagnostics(f, p)[D.NONFINITE] > 0:
+                    flagged = t
+                    break
+        assert (flagged is not None) == diverges, (tau, G, flagged)
