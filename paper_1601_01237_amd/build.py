@@ -44,8 +44,8 @@ def _hipcc():
     return exe
 
 
-def _compile(src, extra):
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+def _compile(src, extra, objdir=OBJDIR):
+    obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
     cmd = [_hipcc(), *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -53,23 +53,35 @@ def _compile(src, extra):
     return obj, r.stderr
 
 
-def build(verbose=False, extra=()):
-    """Compile every source and link liblbm.so; returns the library path."""
-    os.makedirs(OBJDIR, exist_ok=True)
+# AddressSanitizer on the host code only (the device code is built as usual).
+HOST_ASAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build(verbose=False, extra=(), out=None, objdir=None, host_asan=False):
+    """Compile every source and link liblbm.so; returns the library path.
+
+    ``host_asan`` instruments the host code with AddressSanitizer (for the
+    host-side checks of the C ABI); ``out``/``objdir`` place such a build
+    away from the product library."""
+    out = out or LIB
+    objdir = objdir or OBJDIR
+    flags = list(extra) + (HOST_ASAN if host_asan else [])
+    os.makedirs(objdir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        results = list(ex.map(lambda s: _compile(s, list(extra)), SOURCES))
+        results = list(ex.map(lambda s: _compile(s, flags, objdir), SOURCES))
     objs = [o for o, _ in results]
     if verbose:
         for _, err in results:
             if err.strip():
                 print(err, file=sys.stderr)
-    tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    tmp = out + ".tmp"
+    link = ["-Xarch_host", "-fsanitize=address", "-shared-libasan"] if host_asan else []
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *link, *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
