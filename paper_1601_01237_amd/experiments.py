@@ -158,11 +158,11 @@ def wall_droplet(shape=(40, 96, 96), radius=14.0, rho_wall=(0.0, 0.0), G=G_PHYS,
 
 
 def incline_drift(shape=(192, 192, 384), angle=30.0, radius=32.0, G=G_PHYS, tau=1.0, steps=10000,
-                  window=1000, thr=0.515):
+                  window=1000, thr=0.515, collision="bgk"):
     """Droplet on the 30-degree plane of the inclined channel: drift over the last window."""
     nz, ny, nx = shape
     rho0, solid = inputs.inclined_channel(shape, angle_deg=angle, radius=radius, seed=0)
-    sim = Sim(rho0, tau=(tau, tau), G=G, solid=solid)
+    sim = Sim(rho0, tau=(tau, tau), G=G, solid=solid, collision=collision)
     zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     zc = nz / 3.0
     region = (np.sqrt((xx - nx / 2.0) ** 2 + (yy - ny / 2.0) ** 2 + (zz - zc) ** 2) < 2.0 * radius) & ~solid
@@ -177,7 +177,8 @@ def incline_drift(shape=(192, 192, 384), angle=30.0, radius=32.0, G=G_PHYS, tau=
     v, vec = fits.drift_velocity(c0, c1, window)
     fluid = int((~solid).sum())
     return dict(drift=v, drift_vec=vec.tolist(), cells=[n0, n1], droplet_volume_fraction=n1 / fluid,
-                nonfinite=d["nonfinite"], max_uf=d["max_uf"], G=G, tau=tau, steps=steps, window=window)
+                nonfinite=d["nonfinite"], max_uf=d["max_uf"], G=G, tau=tau, steps=steps, window=window,
+                collision=collision)
 
 
 def main():
@@ -199,7 +200,7 @@ def main():
     elif args.case == "wetting":
         res = wetting_sweep(G=args.G, steps=args.steps or 4000, collision=args.collision)
     else:
-        res = incline_drift(G=args.G, steps=args.steps or 10000)
+        res = incline_drift(G=args.G, steps=args.steps or 10000, collision=args.collision)
     print(json.dumps(res, default=float))
 
 

@@ -163,6 +163,43 @@ def test_calibration_gradient_against_central_differences(lib):
     assert abs(ad_r - fd_r) <= 1e-2 * abs(fd_r), (ad_r, fd_r)
 
 
+@pytest.mark.parametrize("n,steps,every", [(96, 500, 50)])
+def test_calibration_gradient_full_size_against_central_differences(lib, n, steps, every):
+    """The differentiation workload at full size: 96^3, R = 20, 500 steps with
+    a checkpoint every 50; dL/dG, dL/dtau and a random direction of dL/drho0
+    against central differences of the FP32 forward (h = 1e-3, as on 16^3:
+    the forward's rounding noise swamps h = 1e-4)."""
+    from paper_1601_01237_amd.autograd import LBMFunction
+    say(f"calibration gradient vs central differences {n}^3 x {steps}")
+    h = 1e-3
+    rho0, target = _calibration_inputs(n)
+    tgt = torch.tensor(target, dtype=torch.float64, device="cuda")
+
+    def loss(G, tau, r0=None):
+        r = torch.tensor(rho0, device="cuda") if r0 is None else r0
+        rho = LBMFunction.apply(r, torch.tensor(G), torch.tensor(tau), steps, every)
+        return 0.5 * ((rho[0].double() - tgt) ** 2).sum()
+
+    G, tau = -1.0, 1.0
+    r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
+    Gt = torch.tensor(G, dtype=torch.float64, requires_grad=True)
+    Tt = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+    L = 0.5 * ((LBMFunction.apply(r0, Gt, Tt, steps, every)[0].double() - tgt) ** 2).sum()
+    L.backward()
+    with torch.no_grad():
+        fd_G = (float(loss(G + h, tau)) - float(loss(G - h, tau))) / (2 * h)
+        fd_t = (float(loss(G, tau + h)) - float(loss(G, tau - h))) / (2 * h)
+        v = torch.tensor(inputs.uniform_noise(rho0.shape, seed=4), device="cuda")
+        fd_r = (float(loss(G, tau, torch.tensor(rho0, device="cuda") + h * v))
+                - float(loss(G, tau, torch.tensor(rho0, device="cuda") - h * v))) / (2 * h)
+    ad_r = float((r0.grad * v).sum())
+    say(f"{n}^3 gradient: dG {float(Gt.grad):.6e} (FD {fd_G:.6e}), dtau {float(Tt.grad):.6e} (FD {fd_t:.6e}), "
+        f"drho0.v {ad_r:.6e} (FD {fd_r:.6e})")
+    assert abs(float(Gt.grad) - fd_G) <= 1e-2 * abs(fd_G), (float(Gt.grad), fd_G)
+    assert abs(float(Tt.grad) - fd_t) <= 1e-2 * abs(fd_t), (float(Tt.grad), fd_t)
+    assert abs(ad_r - fd_r) <= 1e-2 * abs(fd_r), (ad_r, fd_r)
+
+
 def test_adjoint_step_96cube_all_cells(lib):
     """One reverse step of the differentiation workload at its full size
     (96^3 droplet, R = 20, tau = 1, G = -1, automatic tiling as timed),
