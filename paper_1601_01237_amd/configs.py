@@ -122,7 +122,7 @@ def c5(n=96, steps=500, every=50):
     L.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    return [dict(config="C5", shape=[n, n, n], steps=steps, checkpoint_every=every, loss=float(L),
+    return [dict(config="C5", shape=[n, n, n], steps=steps, checkpoint_every=every, loss=float(L.detach()),
                  dL_dG=float(G.grad), dL_dtau=float(tau.grad), dL_drho0_norm=float(rho0.grad.norm()),
                  forward_seconds=t1 - t0, backward_seconds=t2 - t1)]
 
