@@ -44,17 +44,16 @@ template <> struct StorageTraits<Storage::F32> {
   __device__ static inline float encode(float v) { return v; }
 };
 
-// The 16-bit forms store X - w_shift: decode_add reads a stored value back as
-// X, sub_encode rounds X - w_shift to the storage type.  (Mixed-precision
-// FMAs would fuse the FP16 pair into one instruction each, but measured
-// slower on gfx950 than convert plus add.)
+// The 16-bit forms store X - w_shift: decode reads a stored value back as the
+// deviation, encode rounds a deviation to the storage type (the kernels add
+// and subtract w_shift).  (Mixed-precision FMAs would fuse a conversion and
+// the shift into one instruction, but measured slower on gfx950 than convert
+// plus add.)
 template <> struct StorageTraits<Storage::F16> {
   using T = _Float16;
   static constexpr bool shifted = true;
   __device__ static inline float decode(_Float16 v) { return static_cast<float>(v); }
   __device__ static inline _Float16 encode(float v) { return static_cast<_Float16>(v); }
-  __device__ static inline float decode_add(_Float16 v, float ws) { return decode(v) + ws; }
-  __device__ static inline _Float16 sub_encode(float x, float ws) { return encode(x - ws); }
   // Halves of a 32-bit word of a folded row, and the bits of one value.
   __device__ static inline float lo(uint32_t w) {
     return static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(w & 0xffffu)));
@@ -74,8 +73,6 @@ template <> struct StorageTraits<Storage::BF16> {
     return __uint_as_float(static_cast<uint32_t>(v) << 16);
   }
   __device__ static inline uint16_t encode(float v) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v)); }
-  __device__ static inline float decode_add(uint16_t v, float ws) { return decode(v) + ws; }
-  __device__ static inline uint16_t sub_encode(float x, float ws) { return encode(x - ws); }
   __device__ static inline float lo(uint32_t w) { return __uint_as_float(w << 16); }
   __device__ static inline float hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
   __device__ static inline uint32_t bits(uint16_t q) { return q; }
