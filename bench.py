@@ -210,7 +210,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=128)
-    ap.add_argument("--tile", type=int, default=None, help="tile shape of the step kernel (0..5)")
+    ap.add_argument("--tile", type=int, default=None, help="tile shape of the step kernel (0..9, see lbm_set_tiling)")
     ap.add_argument("--zchunk", type=int, default=None, help="z planes per workgroup (0 = default)")
     args = ap.parse_args()
     if args.gpus != 1:

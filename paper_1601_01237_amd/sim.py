@@ -165,7 +165,7 @@ class Sim:
             raise _lib.LBMError(f"lbm_step (t = {self.t}, {int(d['nonfinite'])} cells)", _lib.EUNSTABLE)
 
     def set_tiling(self, tile=-1, zchunk=0):
-        """Tile shape of the step kernel (-1 = automatic, 0..5, see lbm_set_tiling) and z planes per workgroup."""
+        """Tile shape of the step kernel (-1 = automatic, 0..9, see lbm_set_tiling) and z planes per workgroup."""
         _lib.check("lbm_set_tiling", self.lib.lbm_set_tiling(self.ctx, int(tile), int(zchunk)))
 
     @property
