@@ -115,7 +115,7 @@ enum {
 };
 
 typedef struct {
-  int32_t nx, ny, nz;  /* >= 1 each; N * element size must stay below 4 GiB */
+  int32_t nx, ny, nz;  /* >= 1 each; sizes as lbm_state_elems accepts      */
   int32_t storage;     /* lbm_storage                                        */
   double tau[2];       /* relaxation times tau_A, tau_B (Eq. 2), > 1/2       */
   double G[2][2];      /* interaction matrix G^{ab} of Eq. (7), paper sign:  */
@@ -152,7 +152,8 @@ const char *lbm_status_str(lbm_status s);
  * plane-major layout above) for storage `storage` (lbm_storage): nx*ny
  * elements rounded up to 256 bytes, plus 256 bytes when that is a multiple
  * of 64 KiB.  Adjoint arrays use the FP32 value.  Returns -1 for sizes the
- * library does not support.  Pure host call. */
+ * library does not support: one z plane of all 38 populations (38 * S
+ * elements) must stay below 2 GiB.  Pure host call. */
 int64_t lbm_plane_stride(int32_t nx, int32_t ny, int32_t storage);
 
 /* h = nx/2 when rows of storage `storage` are folded (16-bit forms, even
@@ -163,7 +164,9 @@ int32_t lbm_row_half(int32_t nx, int32_t storage, int32_t walls);
 
 /* Elements of one state buffer (buf_a, buf_b, x_t) of storage `storage`, and
  * of one adjoint array (lam) with storage LBM_FP32: 2*19*nz*plane stride.
- * Returns -1 for unsupported sizes.  Pure host call. */
+ * Returns -1 for unsupported sizes: those of lbm_plane_stride, and N cells
+ * with N >= 2^31 or N times the element size >= 4 GiB.  lbm_init answers
+ * LBM_ENOTSUP for exactly these sizes (nx, ny, nz >= 1).  Pure host call. */
 int64_t lbm_state_elems(int32_t nx, int32_t ny, int32_t nz, int32_t storage);
 
 /* Creates a context and writes the rest state at t = 0 into buf_a.

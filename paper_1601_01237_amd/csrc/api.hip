@@ -94,11 +94,22 @@ const char* lbm_status_str(lbm_status s) {
   return "unknown status";
 }
 
+// One z plane of all 38 populations is addressed by a single buffer
+// resource with 32-bit offsets: it must stay below 2 GiB.
+static bool plane_block_fits(uint32_t pstride, size_t es) {
+  return static_cast<uint64_t>(2 * LBM_Q) * pstride * es < (1ull << 31);
+}
+
+// Cell indices are 32-bit inside the kernels, and one population array of N
+// cells is addressed with 32-bit offsets.
+static bool cells_fit(uint64_t n, size_t es) { return n * es < (1ull << 32) && n < (1ull << 31); }
+
 int64_t lbm_plane_stride(int32_t nx, int32_t ny, int32_t storage) {
   if (nx < 1 || ny < 1 || storage < LBM_FP32 || storage > LBM_BF16) return -1;
   const size_t es = elem_size(static_cast<Storage>(storage));
   if (static_cast<uint64_t>(nx) * ny * es >= (1ull << 31)) return -1;
-  return plane_stride(nx, ny, static_cast<int>(es));
+  const uint32_t s = plane_stride(nx, ny, static_cast<int>(es));
+  return plane_block_fits(s, es) ? static_cast<int64_t>(s) : -1;
 }
 
 int32_t lbm_row_half(int32_t nx, int32_t storage, int32_t walls) {
@@ -109,6 +120,8 @@ int32_t lbm_row_half(int32_t nx, int32_t storage, int32_t walls) {
 int64_t lbm_state_elems(int32_t nx, int32_t ny, int32_t nz, int32_t storage) {
   const int64_t s = lbm_plane_stride(nx, ny, storage);
   if (s < 0 || nz < 1) return -1;
+  const uint64_t n = static_cast<uint64_t>(nx) * ny * nz;
+  if (!cells_fit(n, elem_size(static_cast<Storage>(storage)))) return -1;
   return static_cast<int64_t>(2 * LBM_Q) * nz * s;
 }
 
@@ -130,11 +143,9 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
   const uint64_t nxy = static_cast<uint64_t>(p->nx) * p->ny;
   const uint64_t n = nxy * p->nz;
   const Storage st = static_cast<Storage>(p->storage);
-  // Within one population array, offsets are 32-bit; one z plane of all 38
-  // populations is addressed by a single buffer resource.
-  if (n * elem_size(st) >= (1ull << 32) || n >= (1ull << 31)) return LBM_ENOTSUP;
+  if (!cells_fit(n, elem_size(st)) || nxy * elem_size(st) >= (1ull << 31)) return LBM_ENOTSUP;
   const uint32_t pstride = plane_stride(p->nx, p->ny, static_cast<int>(elem_size(st)));
-  if (static_cast<uint64_t>(2 * LBM_Q) * pstride * elem_size(st) >= (1ull << 31)) return LBM_ENOTSUP;
+  if (!plane_block_fits(pstride, elem_size(st))) return LBM_ENOTSUP;
 
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) return LBM_EHIP;

@@ -94,7 +94,8 @@ class Sim:
         self.lam_pstride = int(self.lib.lbm_plane_stride(nx, ny, _lib.FP32))
         self.lam_elems = int(self.lib.lbm_state_elems(nx, ny, nz, _lib.FP32))
         self.row_half = int(self.lib.lbm_row_half(nx, code, int(solid is not None)))
-        if min(self.pstride, self.state_elems, self.lam_elems, self.row_half) < 0:
+        # (the adjoint arrays are FP32 and only used with FP32 storage)
+        if min(self.pstride, self.state_elems, self.row_half) < 0:
             raise ValueError(f"grid {self.shape} is not supported")
 
         with torch.cuda.device(self.device):

@@ -162,6 +162,44 @@ def test_invalid_parameters_are_rejected_before_any_device_call(lib, field, valu
     assert ctx.value is None
 
 
+# (nx, ny, nz, storage, supported): one z plane of all 38 populations below
+# 2 GiB, N < 2^31 cells and N * element size < 4 GiB.
+SIZE_CASES = [
+    (4096, 3440, 4, 0, True),     # 38 * 56.4 MB = 2.14 GB plane block
+    (4096, 3450, 4, 0, False),    # 2.1479e9 >= 2^31
+    (4096, 6880, 4, 1, True),     # the same bytes in 16-bit storage
+    (4096, 6900, 4, 2, False),
+    (1024, 1024, 1023, 0, True),  # N * 4 just below 4 GiB
+    (1024, 1024, 1024, 0, False),
+    (1024, 1024, 2047, 1, True),  # N just below 2^31
+    (1024, 1024, 2048, 1, False),
+]
+
+
+@pytest.mark.parametrize("nx,ny,nz,storage,ok", SIZE_CASES)
+def test_size_limits_agree_with_init(lib, nx, ny, nz, storage, ok):
+    """lbm_state_elems is -1 exactly where lbm_init answers LBM_ENOTSUP for
+    the size; the check comes before any device call."""
+    from paper_1601_01237_amd import _lib
+    es = 4 if storage == _lib.FP32 else 2
+    stride = lib.lbm_plane_stride(nx, ny, storage)
+    elems = lib.lbm_state_elems(nx, ny, nz, storage)
+    if ok:
+        assert stride >= nx * ny and 38 * stride * es < 2 ** 31
+        assert elems == 38 * nz * stride
+    else:
+        assert elems == -1
+    p = _valid_params(_lib)
+    p.nx, p.ny, p.nz, p.storage = nx, ny, nz, storage
+    ctx = ctypes.c_void_p()
+    if not ok:
+        # Only an unsupported size may reach the library here: a supported
+        # one would go on to launch on the dummy pointers.
+        rc = lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000),
+                          None, ctypes.c_void_p(0x3000), None)
+        assert rc == -5 and ctx.value is None
+
+
 def test_status_of_calls_on_a_null_context(lib):
     assert lib.lbm_set_tiling(None, -1, 0) == -1
     assert lib.lbm_moments(None, None, None, None, None) == -1

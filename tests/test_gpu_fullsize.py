@@ -10,6 +10,8 @@ benchmark times (automatic tile shape and z chunk).
   each sampled cell (Eq. 1 streaming, then collision) and its centre is exact.
   The 16-bit forms are compared with the oracle's emulation of the storage
   rounding.
+* The largest x-y planes the library takes (4096 x 3440 in FP32, 4096 x 6880
+  in FP16, 5 planes): the same sampled step, with the last rows sampled.
 * Mass per species over 20 steps at 512^3 (collision and streaming conserve
   it; FP32 reductions in FP64).
 """
@@ -85,13 +87,15 @@ def _centers(shape, solid, seed):
     return np.array(out, dtype=np.int64)
 
 
-def _sampled_step(rho0, tau, G, storage, solid=None, label="", warm=3):
+def _sampled_step(rho0, tau, G, storage, solid=None, label="", warm=3, extra=None):
     from paper_1601_01237_amd.sim import Sim
     shape = rho0.shape[1:]
     say(f"{label}: {storage} sampled one-step parity")
     sim = Sim(rho0, tau=(tau, tau), G=G, storage=storage, solid=solid)
     sim.step(warm)
     centers = _centers(shape, solid, seed=7)
+    if extra is not None:
+        centers = np.concatenate([centers, np.asarray(extra, dtype=np.int64)])
     before = _patches(sim, centers)
     sim.step(1)
     after = _patches(sim, centers)[:, 2, 2, 2]
@@ -136,6 +140,28 @@ def test_512cube_16bit_sampled_step(lib, storage, ulps):
     # the others' roundings.
     assert np.mean(err == 0.0) > 0.95
     assert err.max() <= 19 * ulps * scale
+
+
+@pytest.mark.parametrize("storage,shape", [("fp32", (5, 3440, 4096)), ("fp16", (5, 6880, 4096))])
+def test_largest_plane_sampled_step(lib, storage, shape):
+    """The largest x-y planes the library takes at nx = 4096: one z plane of
+    all 38 populations is 2.14 GB, just under the 2 GiB one buffer resource
+    addresses, so the step's 32-bit offsets inside a plane reach the top of
+    their range.  The samples include the cells of the last rows."""
+    from paper_1601_01237_amd import _lib
+    nz, ny, nx = shape
+    es = 4 if storage == "fp32" else 2
+    stride = lib.lbm_plane_stride(nx, ny, _lib.FP32 if storage == "fp32" else _lib.FP16)
+    assert 0.99 * 2 ** 31 < 38 * stride * es < 2 ** 31
+    rho0, _, _ = inputs.random_droplets(shape, count=512, rmin=8.0, rmax=24.0, seed=3)
+    corners = [(z, y, x) for z in (0, nz - 1) for y in (0, ny - 2, ny - 1) for x in (0, nx // 2 - 1, nx // 2, nx - 1)]
+    err, want, scale = _sampled_step(rho0, 0.6, -1.0, storage, label=f"largest plane {nx}x{ny}x{nz}",
+                                     extra=corners)
+    if storage == "fp32":
+        assert err.max() <= 1e-6 * scale
+    else:
+        assert np.mean(err == 0.0) > 0.95
+        assert err.max() <= 19 * 2.0 ** -10 * scale
 
 
 def test_walls_384x192x192_sampled_step(lib):
