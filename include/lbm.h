@@ -26,21 +26,26 @@
  *   State:    the library keeps the post-collision, pre-streaming populations
  *             X (one buffer per time level, two buffers ping-pong).  At time t
  *             the current state lives in buf_a if t is even, buf_b if odd.
- *             Stored states and adjoint arrays use the plane-major layout
- *             X[z][a][i][y][x]: element (a, i, x, y, z) at index
- *             ((z*2 + a)*19 + i)*S + y*nx + pos(x) with the plane stride
- *             S = lbm_plane_stride(nx, ny, storage) >= nx*ny, so that one z
- *             plane of all 38 populations is one contiguous block.  pos(x)
- *             = x, except for the 16-bit storage forms with even nx and no
- *             walls, whose rows are folded: with h = nx/2 (lbm_row_half),
- *             pos(x) = 2x for
+ *             Stored states and adjoint arrays use the row-blocked layout:
+ *             each z plane is a sequence of blocks of B = lbm_row_block(nx,
+ *             ny, storage) y rows, and a block holds the B rows of population
+ *             (0, 0), then those of (0, 1), ..., (1, 18), S elements apart
+ *             (S = lbm_plane_stride(nx, ny, storage) >= B*nx).  Element
+ *             (a, i, x, y, z) sits at index
+ *               z*Z + (y / B)*38*S + (a*19 + i)*S + (y % B)*nx + pos(x),
+ *             Z = 38*S*ceil(ny / B) elements per z plane.  FP32 takes B = 4
+ *             (or ny if smaller): the 38 population rows a workgroup reads
+ *             from one plane are one contiguous range.  The 16-bit forms
+ *             take B = ny (population planes).  pos(x) = x, except for the
+ *             16-bit storage forms with even nx and no walls, whose rows
+ *             are folded: with h = nx/2 (lbm_row_half), pos(x) = 2x for
  *             x < h and 2(x - h) + 1 for x >= h, so the 32-bit word k of a
- *             row holds cells k and k + h.  The S -
- *             nx*ny elements after each plane are padding (never read):
- *             population planes a large power of two apart would map the rows
- *             a step reads together onto the same DRAM channels.  A state (or
- *             adjoint) buffer holds lbm_state_elems(nx, ny, nz, storage)
- *             elements.
+ *             row holds cells k and k + h.  The S - B*nx elements after each
+ *             population's rows, and the rows past ny in the last block,
+ *             are padding (never read): population blocks a large power of
+ *             two apart would map the rows a step reads together onto the
+ *             same DRAM channels.  A state (or adjoint) buffer holds
+ *             lbm_state_elems(nx, ny, nz, storage) = nz*Z elements.
  *             The pre-collision populations of Eq. (1) at time t are the pull
  *             f_i(x) = X_i(x - c_i), or X_opp(i)(x) if x - c_i is solid.
  *   Memory:   every array pointer is DEVICE memory owned by the caller unless
@@ -148,13 +153,17 @@ lbm_status lbm_velocity_set(int32_t *c, double *w);
 /* Human-readable name of a status code (static string). */
 const char *lbm_status_str(lbm_status s);
 
-/* Elements from one population plane of a stored state to the next (the
- * plane-major layout above) for storage `storage` (lbm_storage): nx*ny
+/* S of the layout above: elements from one population's rows of a row
+ * block to the next population's, for storage `storage` (lbm_storage): B*nx
  * elements rounded up to 256 bytes, plus 256 bytes when that is a multiple
  * of 64 KiB.  Adjoint arrays use the FP32 value.  Returns -1 for sizes the
- * library does not support: one z plane of all 38 populations (38 * S
- * elements) must stay below 2 GiB.  Pure host call. */
+ * library does not support: nx*ny times the element size, and one z plane
+ * of the state (Z elements), must stay below 2 GiB.  Pure host call. */
 int64_t lbm_plane_stride(int32_t nx, int32_t ny, int32_t storage);
+
+/* B of the layout above: y rows per row block (4 or ny for FP32, ny for
+ * the 16-bit forms); -1 where lbm_plane_stride is -1.  Pure host call. */
+int32_t lbm_row_block(int32_t nx, int32_t ny, int32_t storage);
 
 /* h = nx/2 when rows of storage `storage` are folded (16-bit forms, even
  * nx, walls == 0; see pos(x) above), 0 when rows are stored in x order, -1
@@ -163,7 +172,7 @@ int64_t lbm_plane_stride(int32_t nx, int32_t ny, int32_t storage);
 int32_t lbm_row_half(int32_t nx, int32_t storage, int32_t walls);
 
 /* Elements of one state buffer (buf_a, buf_b, x_t) of storage `storage`, and
- * of one adjoint array (lam) with storage LBM_FP32: 2*19*nz*plane stride.
+ * of one adjoint array (lam) with storage LBM_FP32: nz*Z (layout above).
  * Returns -1 for unsupported sizes: those of lbm_plane_stride, and N cells
  * with N >= 2^31 or N times the element size >= 4 GiB.  lbm_init answers
  * LBM_ENOTSUP for exactly these sizes (nx, ny, nz >= 1).  Pure host call. */
@@ -233,7 +242,7 @@ lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t tile, int32_t zchunk);
  * (other storage forms or the regularized collision: LBM_ENOTSUP) 
  * Let X_t be the stored state at t and L a scalar objective.  With
  * lam_{t+1} = dL/dX_{t+1} (device float, lbm_state_elems(nx, ny, nz,
- * LBM_FP32), in the plane-major layout of the stored state) this computes
+ * LBM_FP32), in the layout of an FP32 stored state) this computes
  * lam_t = dL/dX_t, the transpose of one step at X_t (collision with the
  * Eq. 7 gather, then pull streaming with bounce-back).  It also ADDS to
  * dparams (device double[3]): dL/dG (for tied G^{AB} = G^{BA}), dL/dtau_A,
@@ -251,7 +260,7 @@ lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *x_t, const float *lam_in,
 
 /* dL/dX_T for an objective of the densities at time T: given
  * grad_rho (device float, 2*N, index a*N + c) = dL/drho^a(x, T), writes lam
- * (device float, an adjoint array, plane-major) = dL/dX_T.  Solid cells get
+ * (device float, an adjoint array, state layout) = dL/dX_T.  Solid cells get
  * zero. */
 lbm_status lbm_adjoint_seed(lbm_ctx *ctx, const float *grad_rho, float *lam);
 

@@ -56,6 +56,7 @@ def _declare(lib):
         "lbm_velocity_set": (i32, [C.POINTER(C.c_int32), dp]),
         "lbm_status_str": (C.c_char_p, [i32]),
         "lbm_plane_stride": (i64, [i32, i32, i32]),
+        "lbm_row_block": (i32, [i32, i32, i32]),
         "lbm_state_elems": (i64, [i32, i32, i32, i32]),
         "lbm_row_half": (i32, [i32, i32, i32]),
         "lbm_init": (i32, [C.POINTER(vp), C.POINTER(Params), vp, vp, vp, vp, vp]),
@@ -97,7 +98,7 @@ def check(func, code):
         raise LBMError(func, code)
 
 
-EXPORTED = ["lbm_version", "lbm_velocity_set", "lbm_status_str", "lbm_plane_stride",
+EXPORTED = ["lbm_version", "lbm_velocity_set", "lbm_status_str", "lbm_plane_stride", "lbm_row_block",
             "lbm_state_elems", "lbm_row_half", "lbm_init", "lbm_step",
             "lbm_moments", "lbm_get_populations", "lbm_set_populations", "lbm_time",
             "lbm_set_time", "lbm_set_tiling", "lbm_adjoint_work_bytes", "lbm_adjoint_step",

@@ -23,14 +23,14 @@ from . import _lib
 from .sim import Sim, _ptr
 
 
-def to_plane_major(f, sim):
-    """(2, 19, nz, ny, nx) FP32 array -> adjoint array in the plane-major layout of ``sim``."""
-    return sim.to_state_layout(f, sim.lam_pstride, sim.lam_elems)
+def to_adjoint_layout(f, sim):
+    """(2, 19, nz, ny, nx) FP32 array -> adjoint array in the state layout of ``sim``."""
+    return sim.to_state_layout(f, sim.lam_layout, sim.lam_elems)
 
 
-def from_plane_major(x, sim):
-    """Adjoint array (plane-major layout of ``sim``) -> (2, 19, nz, ny, nx)."""
-    return sim.from_state_layout(x, sim.lam_pstride)
+def from_adjoint_layout(x, sim):
+    """Adjoint array (state layout of ``sim``) -> (2, 19, nz, ny, nx)."""
+    return sim.from_state_layout(x, sim.lam_layout)
 
 
 class Reverse:

@@ -48,10 +48,11 @@ __device__ __forceinline__ uint64_t near(const Cell3& c, int dx, int dy, int dz,
   return (z * g.ny + y) * g.nx + x;
 }
 
-// Plane-major index of population (s, i) at (x + dx, y + dy, z + dz).
+// Index of population (s, i) at (x + dx, y + dy, z + dz) in a state-layout array.
 __device__ __forceinline__ uint64_t near_pm(const Cell3& c, int s, int i, int dx, int dy, int dz, const Grid& g) {
-  const uint64_t x = pick(dx, c.xm, c.x, c.xp), y = pick(dy, c.ym, c.y, c.yp), z = pick(dz, c.zm, c.z, c.zp);
-  return ((z * 2 + s) * Q + i) * g.pstride + y * g.nx + x;
+  const uint64_t x = pick(dx, c.xm, c.x, c.xp), z = pick(dz, c.zm, c.z, c.zp);
+  const int y = pick(dy, c.ym, c.y, c.yp);
+  return z * g.zstride + row_off(y, g) + static_cast<uint64_t>(s * Q + i) * g.pstride + x;
 }
 
 // Adjoint, pass 2: A^b(x) = a^b(x) + sum_i w_i c_i . Sbar^b(x - c_i) on fluid x.

@@ -96,8 +96,15 @@ const char* lbm_status_str(lbm_status s) {
 
 // One z plane of all 38 populations is addressed by a single buffer
 // resource with 32-bit offsets: it must stay below 2 GiB.
-static bool plane_block_fits(uint32_t pstride, size_t es) {
-  return static_cast<uint64_t>(2 * LBM_Q) * pstride * es < (1ull << 31);
+static bool plane_block_fits(const Layout& L, size_t es) { return L.zstride * es < (1ull << 31); }
+
+// Layout of a supported plane size, else false.
+static bool layout_of(int32_t nx, int32_t ny, int32_t storage, Layout* L) {
+  if (nx < 1 || ny < 1 || storage < LBM_FP32 || storage > LBM_BF16) return false;
+  const size_t es = elem_size(static_cast<Storage>(storage));
+  if (static_cast<uint64_t>(nx) * ny * es >= (1ull << 31)) return false;
+  *L = state_layout(nx, ny, static_cast<int>(es));
+  return plane_block_fits(*L, es);
 }
 
 // Cell indices are 32-bit inside the kernels, and one population array of N
@@ -105,11 +112,13 @@ static bool plane_block_fits(uint32_t pstride, size_t es) {
 static bool cells_fit(uint64_t n, size_t es) { return n * es < (1ull << 32) && n < (1ull << 31); }
 
 int64_t lbm_plane_stride(int32_t nx, int32_t ny, int32_t storage) {
-  if (nx < 1 || ny < 1 || storage < LBM_FP32 || storage > LBM_BF16) return -1;
-  const size_t es = elem_size(static_cast<Storage>(storage));
-  if (static_cast<uint64_t>(nx) * ny * es >= (1ull << 31)) return -1;
-  const uint32_t s = plane_stride(nx, ny, static_cast<int>(es));
-  return plane_block_fits(s, es) ? static_cast<int64_t>(s) : -1;
+  Layout L;
+  return layout_of(nx, ny, storage, &L) ? static_cast<int64_t>(L.pstride) : -1;
+}
+
+int32_t lbm_row_block(int32_t nx, int32_t ny, int32_t storage) {
+  Layout L;
+  return layout_of(nx, ny, storage, &L) ? static_cast<int32_t>(L.brows) : -1;
 }
 
 int32_t lbm_row_half(int32_t nx, int32_t storage, int32_t walls) {
@@ -118,11 +127,11 @@ int32_t lbm_row_half(int32_t nx, int32_t storage, int32_t walls) {
 }
 
 int64_t lbm_state_elems(int32_t nx, int32_t ny, int32_t nz, int32_t storage) {
-  const int64_t s = lbm_plane_stride(nx, ny, storage);
-  if (s < 0 || nz < 1) return -1;
+  Layout L;
+  if (!layout_of(nx, ny, storage, &L) || nz < 1) return -1;
   const uint64_t n = static_cast<uint64_t>(nx) * ny * nz;
   if (!cells_fit(n, elem_size(static_cast<Storage>(storage)))) return -1;
-  return static_cast<int64_t>(2 * LBM_Q) * nz * s;
+  return static_cast<int64_t>(nz) * static_cast<int64_t>(L.zstride);
 }
 
 lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, const uint8_t* solid,
@@ -143,9 +152,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
   const uint64_t nxy = static_cast<uint64_t>(p->nx) * p->ny;
   const uint64_t n = nxy * p->nz;
   const Storage st = static_cast<Storage>(p->storage);
-  if (!cells_fit(n, elem_size(st)) || nxy * elem_size(st) >= (1ull << 31)) return LBM_ENOTSUP;
-  const uint32_t pstride = plane_stride(p->nx, p->ny, static_cast<int>(elem_size(st)));
-  if (!plane_block_fits(pstride, elem_size(st))) return LBM_ENOTSUP;
+  Layout L;
+  if (!cells_fit(n, elem_size(st)) || !layout_of(p->nx, p->ny, p->storage, &L)) return LBM_ENOTSUP;
 
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) return LBM_EHIP;
@@ -153,7 +161,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
   // 16-bit rows with even nx and no walls are stored folded (two cells per
   // 32-bit word, stepped by the paired march).
   const uint32_t half = static_cast<uint32_t>(lbm_row_half(p->nx, p->storage, solid != nullptr));
-  c->g = Grid{p->nx, p->ny, p->nz, static_cast<uint32_t>(nxy), n, pstride, half};
+  c->g = Grid{p->nx, p->ny, p->nz, static_cast<uint32_t>(nxy), n, L.pstride, half, L.brows,
+               static_cast<uint32_t>(L.zstride)};
   for (int a = 0; a < 2; ++a) {
     c->ph.omega[a] = static_cast<float>(1.0 / p->tau[a]);
     c->ph.rho_wall[a] = static_cast<float>(p->rho_wall[a]);

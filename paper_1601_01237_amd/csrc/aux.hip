@@ -36,13 +36,15 @@ __device__ __forceinline__ uint64_t shifted(const Coord& p, int dx, int dy, int 
   return (z * g.ny + y) * g.nx + x;
 }
 
-// Plane-major index of population (s, i) at cell (x, y, z) + (dx, dy, dz):
-// X[z][s][i][y][pos(x)], i.e. ((z * 2 + s) * 19 + i) * pstride + y * nx +
-// pos(x), with pos the row position of the storage form (folded 16-bit rows).
+// State-layout index of population (s, i) at cell (x, y, z) + (dx, dy, dz):
+// z * zstride + (y / brows) * 38 * pstride + (s * 19 + i) * pstride +
+// (y % brows) * nx + pos(x), with pos the row position of the storage form
+// (folded 16-bit rows).
 template <typename T>
 __device__ __forceinline__ uint64_t pm_at(int s, int i, const Coord& p, int dx, int dy, int dz, const Grid& g) {
   const uint64_t x = wrap_u(p.x + dx, g.nx), y = wrap_u(p.y + dy, g.ny), z = wrap_u(p.z + dz, g.nz);
-  return ((z * 2 + s) * Q + i) * g.pstride + y * g.nx + row_pos<T>(static_cast<int>(x), g);
+  return z * g.zstride + row_off(static_cast<int>(y), g) + static_cast<uint64_t>(s * Q + i) * g.pstride +
+         row_pos<T>(static_cast<int>(x), g);
 }
 
 // Canonical SoA index (s * 19 + i) * N + c of the FP32 population interface.
@@ -198,10 +200,10 @@ __global__ void __launch_bounds__(512) march_copy_kernel(const Grid g, const Til
   const int x = bxx * 128 + static_cast<int>(threadIdx.x & 127u);
   const int y = byy * 4 + static_cast<int>(threadIdx.x >> 7);
   if (x >= g.nx || y >= g.ny) return;  // no barriers below
-  const uint64_t col = static_cast<uint64_t>(y) * g.nx + x;
+  const uint64_t col = row_off(y, g) + static_cast<uint64_t>(x);
   const int z1 = min((bz + 1) * tl.zchunk, g.nz);
   for (int z = bz * tl.zchunk; z < z1; ++z) {
-    const uint64_t base = static_cast<uint64_t>(z) * 2 * Q * g.pstride + col;
+    const uint64_t base = static_cast<uint64_t>(z) * g.zstride + col;
     T v[2 * Q];
 #pragma unroll
     for (int i = 0; i < 2 * Q; ++i) v[i] = src[base + static_cast<uint64_t>(i) * g.pstride];
@@ -219,11 +221,16 @@ unsigned grid_for(uint64_t n) {
 
 }  // namespace
 
-uint32_t plane_stride(int nx, int ny, int elem_bytes) {
-  const uint64_t bytes = static_cast<uint64_t>(nx) * ny * elem_bytes;
+Layout state_layout(int nx, int ny, int elem_bytes) {
+  Layout L;
+  L.brows = static_cast<uint32_t>(elem_bytes == 4 ? (ny < 4 ? ny : 4) : ny);
+  const uint64_t bytes = static_cast<uint64_t>(nx) * L.brows * elem_bytes;
   uint64_t padded = ((bytes + 255) / 256) * 256;
   if (padded % 65536 == 0) padded += 256;
-  return static_cast<uint32_t>(padded / elem_bytes);
+  L.pstride = static_cast<uint32_t>(padded / elem_bytes);
+  const uint64_t blocks = (static_cast<uint64_t>(ny) + L.brows - 1) / L.brows;
+  L.zstride = static_cast<uint64_t>(2 * Q) * L.pstride * blocks;
+  return L;
 }
 
 hipError_t launch_links(const Grid& g, const uint8_t* solid, uint32_t* links, hipStream_t st) {

@@ -1,6 +1,6 @@
 // Addressing helpers shared by the z-marching kernels: XCD-aware block
 // order, periodic wrap, per-column byte offsets and buffer resources over one
-// z plane of the plane-major population layout X[z][a][i][y][x].
+// z plane of the row-blocked population layout (Grid).
 #pragma once
 
 #include "launch.h"
@@ -36,9 +36,18 @@ __device__ __forceinline__ uint32_t row_pos(int gx, const Grid& g) {
   return static_cast<uint32_t>(gx);
 }
 
+// Element offset of row y inside one z plane, population (0, 0); the other
+// populations of the row are pstride elements apart.  One division per
+// column, outside the z march.
+__device__ __forceinline__ uint32_t row_off(int y, const Grid& g) {
+  const uint32_t yy = static_cast<uint32_t>(y);
+  const uint32_t q = yy / g.brows;
+  return q * (2u * Q) * g.pstride + (yy - q * g.brows) * static_cast<uint32_t>(g.nx);
+}
+
 // Wrapped coordinates of one cell column (x, y) and of its x/y neighbours,
-// as BYTE offsets inside one population plane (nx * ny elements), and the
-// column's cell index y * nx + x.
+// as BYTE offsets inside one z plane (population (0, 0)), and the column's
+// cell index y * nx + x.
 struct Column {
   uint32_t x[3];  // row positions of (x-1, x, x+1), times sizeof(T)
   uint32_t y[3];  // ((y-1), y, (y+1)) * nx * sizeof(T)
@@ -55,22 +64,20 @@ __device__ __forceinline__ Column make_column(int ex, int ey, const Grid& g) {
   c.x[2] = row_pos<T>(gx == g.nx - 1 ? 0 : gx + 1, g) * sz;
   const int ym = gy == 0 ? g.ny - 1 : gy - 1;
   const int yp = gy == g.ny - 1 ? 0 : gy + 1;
-  c.y[0] = static_cast<uint32_t>(ym) * g.nx * sz;
-  c.y[1] = static_cast<uint32_t>(gy) * g.nx * sz;
-  c.y[2] = static_cast<uint32_t>(yp) * g.nx * sz;
+  c.y[0] = row_off(ym, g) * sz;
+  c.y[1] = row_off(gy, g) * sz;
+  c.y[2] = row_off(yp, g) * sz;
   c.cell = static_cast<uint32_t>(gy) * g.nx + static_cast<uint32_t>(gx);
   return c;
 }
 
-// Buffer resource over the 38 population planes of z plane `zw`
-// (plane-major layout X[z][a][i][y][x], population planes g.pstride elements
-// apart).  Out-of-range offsets read as zero
-// instead of faulting.
+// Buffer resource over z plane `zw` of a state (g.zstride elements).
+// Out-of-range offsets read as zero instead of faulting.
 constexpr int RSRC_FLAGS = 0x00020000;  // 32-bit data format, gfx9 family
 
 template <typename T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* buf, int zw, const Grid& g) {
-  const uint64_t block = static_cast<uint64_t>(2 * Q) * g.pstride * sizeof(T);
+  const uint64_t block = static_cast<uint64_t>(g.zstride) * sizeof(T);
   const char* base = static_cast<const char*>(buf) + static_cast<uint64_t>(zw) * block;
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), static_cast<short>(0),
                                            static_cast<int>(block), RSRC_FLAGS);

@@ -9,20 +9,36 @@
 namespace lbm {
 
 // Per-launch description of the grid and the physics, shared by every kernel.
+// The stored state of one z plane is a sequence of row blocks of `brows` y
+// rows each; a row block holds, population after population, the rows of
+// all 38 populations (pstride elements apart).  Element (a, i, x, y, z) sits
+// at z * zstride + (y / brows) * 38 * pstride + (a * 19 + i) * pstride +
+// (y % brows) * nx + pos(x).
 struct Grid {
   int nx, ny, nz;
   uint32_t nxy;      // nx * ny
   uint64_t n;        // nx * ny * nz
-  uint32_t pstride;  // elements from one population plane to the next (>= nxy, padded)
+  uint32_t pstride;  // elements from one population's rows of a row block to the next
   uint32_t half;     // nx / 2 when rows of the 16-bit forms are folded (even nx), else 0
+  uint32_t brows;    // y rows per row block
+  uint32_t zstride;  // elements of one z plane: 38 * pstride * ceil(ny / brows)
 };
 
-// Elements per population plane of the stored state for a storage element
-// size: the plane rounded up to 256 bytes, plus 256 bytes when that is a
-// multiple of 64 KiB.  Planes a large power of two apart put the rows a step
-// reads together on the same DRAM channels (measured: 4-5% of step time at
-// 128^2 and 512^2 planes); other plane sizes are left unpadded.
-uint32_t plane_stride(int nx, int ny, int elem_bytes);
+// Layout of the stored state (and of the FP32 adjoint arrays) for a storage
+// element size.  FP32 takes row blocks of 4 rows: the 38 population rows a
+// workgroup of a few rows reads in one plane are then one contiguous range
+// (measured 2-5% faster steps than whole population planes).  The 16-bit
+// forms keep one block per plane (brows = ny): their paired march measured
+// 1.5% slower on 4-row blocks.  pstride is brows * nx rounded up to 256
+// bytes, plus 256 bytes when that is a multiple of 64 KiB (population blocks
+// a large power of two apart put the rows a step reads together on the same
+// DRAM channels: 4-5% of step time at 128^2 and 512^2 planes).
+struct Layout {
+  uint32_t brows;
+  uint32_t pstride;
+  uint64_t zstride;
+};
+Layout state_layout(int nx, int ny, int elem_bytes);
 
 struct Phys {
   float omega[2];     // 1 / tau_a

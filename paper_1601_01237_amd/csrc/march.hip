@@ -16,11 +16,13 @@
 //   Moments  rho^a and u_F fields plus FP64 per-workgroup diagnostic sums;
 //   Adjoint  per-cell transposed collision (see below) for one reverse step.
 //
-// Memory layout: plane-major X[z][a][i][y][pos(x)] (pos(x) = x except on
-// folded 16-bit rows, see buffer.h), so each population load of a 64-wide
-// row is one contiguous 256-byte run (FP32) and one z plane
-// of all 38 populations is one contiguous block; population planes are padded
-// (Grid::pstride) so that they are not a power of two apart.  Blocks are remapped
+// Memory layout: row blocks of Grid::brows rows per z plane, each holding
+// the rows of all 38 populations (launch.h; pos(x) = x except on folded
+// 16-bit rows, see buffer.h), so each population load of a 64-wide row is
+// one contiguous 256-byte run (FP32), the 38 population rows of a few y rows
+// are one contiguous range and one z plane is one contiguous block;
+// population blocks are padded (Grid::pstride) so that they are not a power
+// of two apart.  Blocks are remapped
 // so that the tiles dispatched to one XCD (block id mod 8) are contiguous in
 // x and y and share that XCD's L2 for the halo re-reads.
 

@@ -52,10 +52,9 @@ __device__ __forceinline__ PairColumn make_pair_column(int d, int ey, const Grid
   const int gy = wrap(ey, g.ny);
   const int ym = gy == 0 ? g.ny - 1 : gy - 1;
   const int yp = gy == g.ny - 1 ? 0 : gy + 1;
-  const uint32_t row = static_cast<uint32_t>(g.nx) * 2u;
-  c.y[0] = static_cast<uint32_t>(ym) * row;
-  c.y[1] = static_cast<uint32_t>(gy) * row;
-  c.y[2] = static_cast<uint32_t>(yp) * row;
+  c.y[0] = row_off(ym, g) * 2u;
+  c.y[1] = row_off(gy, g) * 2u;
+  c.y[2] = row_off(yp, g) * 2u;
   return c;
 }
 

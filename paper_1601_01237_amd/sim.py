@@ -88,14 +88,16 @@ class Sim:
         p.collision = self.COLLISIONS[collision]
         self.params = p
 
-        # Plane-major state layout with padded population planes (lbm.h).
+        # Row-blocked state layout (lbm.h): (rows per block, population stride).
         self.pstride = int(self.lib.lbm_plane_stride(nx, ny, code))
+        self.layout = (int(self.lib.lbm_row_block(nx, ny, code)), self.pstride)
         self.state_elems = int(self.lib.lbm_state_elems(nx, ny, nz, code))
-        self.lam_pstride = int(self.lib.lbm_plane_stride(nx, ny, _lib.FP32))
+        self.lam_layout = (int(self.lib.lbm_row_block(nx, ny, _lib.FP32)),
+                           int(self.lib.lbm_plane_stride(nx, ny, _lib.FP32)))
         self.lam_elems = int(self.lib.lbm_state_elems(nx, ny, nz, _lib.FP32))
         self.row_half = int(self.lib.lbm_row_half(nx, code, int(solid is not None)))
         # (the adjoint arrays are FP32 and only used with FP32 storage)
-        if min(self.pstride, self.state_elems, self.row_half) < 0:
+        if min(self.pstride, *self.layout, self.state_elems, self.row_half) < 0:
             raise ValueError(f"grid {self.shape} is not supported")
 
         with torch.cuda.device(self.device):
@@ -174,36 +176,64 @@ class Sim:
         """The stored (post-collision) buffer of the current time level."""
         return self.bufs[self.t & 1]
 
-    def plane_view(self, flat, pstride=None):
-        """(nz, 2, 19, ny, nx) view of a flat plane-major buffer in stored row
-        order: the last index is the row position (see :attr:`x_pos`)."""
+    def plane_view(self, flat, layout=None):
+        """(nz, nyb, 2, 19, B, nx) view of a flat state-layout buffer: z plane,
+        row block, species, population, row in the block, row position (see
+        :attr:`x_pos`).  Rows past ny in the last block are padding."""
         nz, ny, nx = self.shape
-        ps = self.pstride if pstride is None else pstride
-        return flat.view(nz, 2, Q, ps)[..., : nx * ny].unflatten(-1, (ny, nx))
+        b, ps = self.layout if layout is None else layout
+        nyb = -(-ny // b)
+        return flat.view(nz, nyb, 2, Q, ps)[..., : b * nx].unflatten(-1, (b, nx))
+
+    def live_mask(self, layout=None, dtype=None):
+        """Boolean flat mask of the elements of a state-layout buffer that hold
+        a population value (not padding)."""
+        b, ps = self.layout if layout is None else layout
+        nz, ny, nx = self.shape
+        n = nz * -(-ny // b) * 2 * Q * ps
+        m = torch.zeros(n, dtype=torch.bool, device=self.device)
+        v = self.plane_view(m, (b, ps))
+        for yb in range(v.shape[1]):
+            v[:, yb, :, :, : min(b, ny - yb * b)] = True
+        return m
 
     def _row_order(self, flat):
         # the stored state is folded for 16-bit rows; adjoint arrays (FP32) never are
         return self.row_half and flat.dtype != torch.float32
 
-    def to_state_layout(self, f, pstride=None, elems=None):
-        """(2, 19, nz, ny, nx) array -> new flat plane-major buffer (zero padding)."""
+    def cells(self, flat, z, y, x, layout=None):
+        """Values (..., 2, 19) of a state-layout buffer at integer cell
+        coordinates z, y, x (tensors of one shape, on the buffer's device)."""
+        b, _ = self.layout if layout is None else layout
+        if self._row_order(flat):
+            x = self.x_pos.to(flat.device)[x]
+        v = self.plane_view(flat, layout)
+        return v[z, torch.div(y, b, rounding_mode="floor"), :, :, y % b, x]
+
+    def to_state_layout(self, f, layout=None, elems=None):
+        """(2, 19, nz, ny, nx) array -> new flat state-layout buffer (zero padding)."""
         nz, ny, nx = self.shape
-        ps = self.pstride if pstride is None else pstride
+        b, ps = self.layout if layout is None else layout
+        nyb = -(-ny // b)
         n = self.state_elems if elems is None else elems
         out = torch.zeros(n, dtype=f.dtype, device=f.device)
-        src = f.reshape(2, Q, nz, ny, nx).permute(2, 0, 1, 3, 4)
+        rows = torch.zeros((2, Q, nz, nyb * b, nx), dtype=f.dtype, device=f.device)
+        src = f.reshape(2, Q, nz, ny, nx)
         if self._row_order(out):
-            self.plane_view(out, ps)[..., self.x_pos.to(f.device)] = src
+            rows[:, :, :, :ny, self.x_pos.to(f.device)] = src
         else:
-            self.plane_view(out, ps).copy_(src)
+            rows[:, :, :, :ny] = src
+        self.plane_view(out, (b, ps)).copy_(rows.view(2, Q, nz, nyb, b, nx).permute(2, 3, 0, 1, 4, 5))
         return out
 
-    def from_state_layout(self, flat, pstride=None):
-        """Flat plane-major buffer -> (2, 19, nz, ny, nx) contiguous copy (cell order)."""
-        v = self.plane_view(flat, pstride)
+    def from_state_layout(self, flat, layout=None):
+        """Flat state-layout buffer -> (2, 19, nz, ny, nx) contiguous copy (cell order)."""
+        nz, ny, nx = self.shape
+        v = self.plane_view(flat, layout)                   # (nz, nyb, 2, Q, b, nx)
+        rows = v.permute(2, 3, 0, 1, 4, 5).reshape(2, Q, nz, -1, nx)[:, :, :, :ny]
         if self._row_order(flat):
-            v = v[..., self.x_pos.to(flat.device)]
-        return v.permute(1, 2, 0, 3, 4).contiguous()
+            rows = rows[..., self.x_pos.to(flat.device)]
+        return rows.contiguous()
 
     # -- observables -------------------------------------------------------------
     def moments(self, region=None, want_fields=True):

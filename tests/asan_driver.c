@@ -23,8 +23,11 @@ int main(void) {
   EXPECT(lbm_velocity_set(c, w) == LBM_OK);
   EXPECT(lbm_velocity_set(NULL, NULL) == LBM_OK);
   for (int s = -6; s <= 1; ++s) EXPECT(lbm_status_str((lbm_status)s) != NULL && strlen(lbm_status_str((lbm_status)s)) > 0);
-  EXPECT(lbm_plane_stride(128, 128, LBM_FP32) >= 128 * 128);
+  EXPECT(lbm_plane_stride(128, 128, LBM_FP32) >= 4 * 128);
+  EXPECT(lbm_plane_stride(128, 128, LBM_FP16) >= 128 * 128);
   EXPECT(lbm_plane_stride(0, 4, LBM_FP32) == -1);
+  EXPECT(lbm_row_block(128, 128, LBM_FP32) == 4);
+  EXPECT(lbm_row_block(128, 128, LBM_FP16) == 128);
   EXPECT(lbm_state_elems(70, 19, 7, LBM_BF16) > 0);
   EXPECT(lbm_state_elems(4, 4, 0, LBM_FP32) == -1);
   EXPECT(lbm_row_half(64, LBM_FP16, 0) == 32);

@@ -91,24 +91,35 @@ def test_parameter_checks_without_a_gpu(lib):
     assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), dummy_a, dummy_b, None, dummy_r, None) == -5
 
 
+def _layout(nx, ny, es):
+    """(rows per block B, population stride S, z-plane elements Z) of the
+    row-blocked state layout: B = min(4, ny) rows for FP32 and ny for the
+    16-bit forms; B*nx elements rounded up to 256 bytes, plus 256 bytes when
+    that is a multiple of 64 KiB; 38 S per block, ceil(ny / B) blocks."""
+    b = min(4, ny) if es == 4 else ny
+    nbytes = b * nx * es
+    padded = -(-nbytes // 256) * 256
+    if padded % 65536 == 0:
+        padded += 256
+    s = padded // es
+    return b, s, 38 * s * -(-ny // b)
+
+
 def test_plane_stride_and_state_size(lib):
-    """Padded plane-major layout: each population plane rounded up to 256 bytes,
-    plus 256 bytes when that is a multiple of 64 KiB."""
     from paper_1601_01237_amd import _lib
     for nx, ny, st, es in [(128, 128, _lib.FP32, 4), (128, 128, _lib.FP16, 2), (96, 96, _lib.FP32, 4),
                            (70, 19, _lib.BF16, 2), (512, 512, _lib.FP32, 4), (1, 1, _lib.FP32, 4),
-                           (32, 30, _lib.FP32, 4), (384, 192, _lib.FP32, 4), (256, 256, _lib.BF16, 2)]:
-        nbytes = nx * ny * es
-        padded = -(-nbytes // 256) * 256
-        if padded % 65536 == 0:
-            padded += 256
-        want = padded // es
+                           (32, 30, _lib.FP32, 4), (384, 192, _lib.FP32, 4), (256, 256, _lib.BF16, 2),
+                           (130, 9, _lib.FP32, 4), (40, 2, _lib.FP32, 4), (4096, 4, _lib.FP32, 4)]:
+        b, want, z = _layout(nx, ny, es)
+        assert lib.lbm_row_block(nx, ny, st) == b, (nx, ny, st)
         got = lib.lbm_plane_stride(nx, ny, st)
         assert got == want, (nx, ny, st, got, want)
-        assert got >= nx * ny and (got * es) % 65536 != 0
-        assert lib.lbm_state_elems(nx, ny, 7, st) == 2 * 19 * 7 * want
+        assert got >= b * nx and (got * es) % 65536 != 0
+        assert lib.lbm_state_elems(nx, ny, 7, st) == 7 * z
     assert lib.lbm_plane_stride(0, 4, _lib.FP32) == -1
     assert lib.lbm_plane_stride(4, 4, 3) == -1
+    assert lib.lbm_row_block(4, 0, _lib.FP32) == -1
     assert lib.lbm_state_elems(4, 4, 0, _lib.FP32) == -1
 
 
@@ -162,12 +173,12 @@ def test_invalid_parameters_are_rejected_before_any_device_call(lib, field, valu
     assert ctx.value is None
 
 
-# (nx, ny, nz, storage, supported): one z plane of all 38 populations below
-# 2 GiB, N < 2^31 cells and N * element size < 4 GiB.
+# (nx, ny, nz, storage, supported): one z plane of the state below 2 GiB,
+# N < 2^31 cells and N * element size < 4 GiB.
 SIZE_CASES = [
-    (4096, 3440, 4, 0, True),     # 38 * 56.4 MB = 2.14 GB plane block
-    (4096, 3450, 4, 0, False),    # 2.1479e9 >= 2^31
-    (4096, 6880, 4, 1, True),     # the same bytes in 16-bit storage
+    (4096, 3424, 4, 0, True),     # 856 row blocks of 38 * 65,792 B = 2.140e9 B per z plane
+    (4096, 3440, 4, 0, False),    # 860 blocks: 2.150e9 >= 2^31
+    (4096, 6880, 4, 1, True),     # 38 * 56.4 MB population planes = 2.142e9 B
     (4096, 6900, 4, 2, False),
     (1024, 1024, 1023, 0, True),  # N * 4 just below 4 GiB
     (1024, 1024, 1024, 0, False),
@@ -185,8 +196,9 @@ def test_size_limits_agree_with_init(lib, nx, ny, nz, storage, ok):
     stride = lib.lbm_plane_stride(nx, ny, storage)
     elems = lib.lbm_state_elems(nx, ny, nz, storage)
     if ok:
-        assert stride >= nx * ny and 38 * stride * es < 2 ** 31
-        assert elems == 38 * nz * stride
+        b, s, z = _layout(nx, ny, es)
+        assert stride == s and z * es < 2 ** 31
+        assert elems == nz * z
     else:
         assert elems == -1
     p = _valid_params(_lib)

@@ -32,7 +32,7 @@ def _random_state(shape, seed, solid=None):
 
 @pytest.mark.parametrize("walls", [False, True])
 def test_one_adjoint_step_matches_oracle(lib, walls):
-    from paper_1601_01237_amd.autograd import Reverse, from_plane_major, to_plane_major
+    from paper_1601_01237_amd.autograd import Reverse, from_adjoint_layout, to_adjoint_layout
     from paper_1601_01237_amd.sim import Sim
     say(f"adjoint one step walls={walls}")
     shape = (7, 9, 70)
@@ -53,8 +53,8 @@ def test_one_adjoint_step_matches_oracle(lib, walls):
     lam1 = lam1.astype(np.float32)
     rev = Reverse(sim)
     x_t = sim.state
-    lam_gpu, drho = rev.step(x_t, to_plane_major(torch.from_numpy(lam1).cuda(), sim), want_drho0=True)
-    got = from_plane_major(lam_gpu, sim).cpu().numpy()
+    lam_gpu, drho = rev.step(x_t, to_adjoint_layout(torch.from_numpy(lam1).cuda(), sim), want_drho0=True)
+    got = from_adjoint_layout(lam_gpu, sim).cpu().numpy()
 
     mu, dG, dtau = oadj.collide_adjoint(f, lam1.astype(np.float64), p, solid)
     want = oadj.stream_adjoint(mu, solid)
@@ -78,7 +78,7 @@ def test_one_adjoint_step_matches_oracle(lib, walls):
 
 
 def test_seed_matches_oracle(lib):
-    from paper_1601_01237_amd.autograd import Reverse, from_plane_major
+    from paper_1601_01237_amd.autograd import Reverse, from_adjoint_layout
     from paper_1601_01237_amd.sim import Sim
     say("adjoint seed")
     shape = (8, 6, 10)
@@ -91,7 +91,7 @@ def test_seed_matches_oracle(lib):
     g = np.random.default_rng(3).normal(size=(2,) + shape)
     g[:, solid] = 0.0
     lam = Reverse(sim).seed(torch.from_numpy(g))
-    got = from_plane_major(lam, sim).cpu().numpy()
+    got = from_adjoint_layout(lam, sim).cpu().numpy()
     lam_f = np.repeat(g[:, None], 19, axis=1)
     want = oadj.stream_adjoint(lam_f, solid)
     assert rel_err(got, want) < 1e-6
@@ -204,7 +204,7 @@ def test_adjoint_step_96cube_all_cells(lib):
     """One reverse step of the differentiation workload at its full size
     (96^3 droplet, R = 20, tau = 1, G = -1, automatic tiling as timed),
     every cell against the oracle."""
-    from paper_1601_01237_amd.autograd import Reverse, from_plane_major, to_plane_major
+    from paper_1601_01237_amd.autograd import Reverse, from_adjoint_layout, to_adjoint_layout
     from paper_1601_01237_amd.sim import Sim
     say("adjoint one step 96^3")
     n = 96
@@ -215,8 +215,8 @@ def test_adjoint_step_96cube_all_cells(lib):
     f = sim.populations().cpu().numpy().astype(np.float64)   # pre-collision f at t = 20
     lam1 = np.random.default_rng(9).normal(size=f.shape).astype(np.float32)
     rev = Reverse(sim)
-    lam_gpu, drho = rev.step(sim.state, to_plane_major(torch.from_numpy(lam1).cuda(), sim), want_drho0=True)
-    got = from_plane_major(lam_gpu, sim).cpu().numpy()
+    lam_gpu, drho = rev.step(sim.state, to_adjoint_layout(torch.from_numpy(lam1).cuda(), sim), want_drho0=True)
+    got = from_adjoint_layout(lam_gpu, sim).cpu().numpy()
     d = rev.dparams.cpu().numpy()
     sim.close()
     mu, dG, dtau = oadj.collide_adjoint(f, lam1.astype(np.float64), p)

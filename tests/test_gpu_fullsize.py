@@ -10,7 +10,7 @@ benchmark times (automatic tile shape and z chunk).
   each sampled cell (Eq. 1 streaming, then collision) and its centre is exact.
   The 16-bit forms are compared with the oracle's emulation of the storage
   rounding.
-* The largest x-y planes the library takes (4096 x 3440 in FP32, 4096 x 6880
+* The largest x-y planes the library takes (4096 x 3424 in FP32, 4096 x 6880
   in FP16, 5 planes): the same sampled step, with the last rows sampled.
 * Mass per species over 20 steps at 512^3 (collision and streaming conserve
   it; FP32 reductions in FP64).
@@ -56,16 +56,16 @@ def _decode(raw, storage, shift):
 def _patches(sim, centers):
     """Stored values of the 5^3 periodic patches around ``centers`` -> (S, 5, 5, 5, 2, 19)."""
     nz, ny, nx = sim.shape
-    st = sim.plane_view(sim.state)
+    st = sim.state
     d = torch.arange(-2, 3, device=st.device)
     c = torch.as_tensor(centers, device=st.device)
     zi = (c[:, 0, None] + d[None, :]) % nz
     yi = (c[:, 1, None] + d[None, :]) % ny
-    xi = sim.x_pos[(c[:, 2, None] + d[None, :]) % nx]  # row positions (folded 16-bit rows)
+    xi = (c[:, 2, None] + d[None, :]) % nx
     zz = zi[:, :, None, None].expand(-1, 5, 5, 5)
     yy = yi[:, None, :, None].expand(-1, 5, 5, 5)
     xx = xi[:, None, None, :].expand(-1, 5, 5, 5)
-    return st[zz, :, :, yy, xx]
+    return sim.cells(st, zz, yy, xx)
 
 
 def _centers(shape, solid, seed):
@@ -142,17 +142,19 @@ def test_512cube_16bit_sampled_step(lib, storage, ulps):
     assert err.max() <= 19 * ulps * scale
 
 
-@pytest.mark.parametrize("storage,shape", [("fp32", (5, 3440, 4096)), ("fp16", (5, 6880, 4096))])
+@pytest.mark.parametrize("storage,shape", [("fp32", (5, 3424, 4096)), ("fp16", (5, 6880, 4096))])
 def test_largest_plane_sampled_step(lib, storage, shape):
     """The largest x-y planes the library takes at nx = 4096: one z plane of
-    all 38 populations is 2.14 GB, just under the 2 GiB one buffer resource
+    the state is 2.14 GB, just under the 2 GiB one buffer resource
     addresses, so the step's 32-bit offsets inside a plane reach the top of
     their range.  The samples include the cells of the last rows."""
     from paper_1601_01237_amd import _lib
     nz, ny, nx = shape
     es = 4 if storage == "fp32" else 2
-    stride = lib.lbm_plane_stride(nx, ny, _lib.FP32 if storage == "fp32" else _lib.FP16)
-    assert 0.99 * 2 ** 31 < 38 * stride * es < 2 ** 31
+    code = _lib.FP32 if storage == "fp32" else _lib.FP16
+    zplane = lib.lbm_state_elems(nx, ny, 1, code)
+    assert 0.99 * 2 ** 31 < zplane * es < 2 ** 31
+    assert lib.lbm_state_elems(nx, ny + 32, 1, code) == -1
     rho0, _, _ = inputs.random_droplets(shape, count=512, rmin=8.0, rmax=24.0, seed=3)
     corners = [(z, y, x) for z in (0, nz - 1) for y in (0, ny - 2, ny - 1) for x in (0, nx // 2 - 1, nx // 2, nx - 1)]
     err, want, scale = _sampled_step(rho0, 0.6, -1.0, storage, label=f"largest plane {nx}x{ny}x{nz}",

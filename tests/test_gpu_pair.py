@@ -108,7 +108,7 @@ def test_folded_state_layout_round_trip(lib):
     flat = sim.to_state_layout(x.to(torch.float16).cuda())
     back = sim.from_state_layout(flat).float().cpu()
     assert torch.equal(back, x.to(torch.float16).float())
-    raw = sim.plane_view(flat)[0, 0, 0, 0].float().cpu()
+    raw = sim.plane_view(flat)[0, 0, 0, 0, 0].float().cpu()  # z 0, block 0, A, i = 0, row 0
     want = torch.tensor([0, 5, 1, 6, 2, 7, 3, 8, 4, 9], dtype=torch.float32) * 0.01
     assert torch.equal(raw, want.to(torch.float16).float())
     sim.close()

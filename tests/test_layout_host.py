@@ -1,0 +1,111 @@
+"""Host-side logic of the row-blocked state layout (no GPU): the layout
+queries of the C ABI and the Python helpers that move arrays in and out of
+that layout (Sim.to_state_layout / from_state_layout / cells / live_mask),
+checked against the index formula of the public header."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+Q = 19
+LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1601_01237_amd", "liblbm.so")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    """The library for its pure host calls (no GPU needed)."""
+    if not os.path.exists(LIB):
+        pytest.fail("liblbm.so is not built (run __graft_entry__.build())")
+    from paper_1601_01237_amd import _lib
+    return _lib.load()
+
+
+def _host_sim(lib, shape, storage):
+    """A Sim carrying only the layout attributes (built from the pure host
+    queries), enough for its layout helpers on CPU tensors."""
+    from paper_1601_01237_amd import _lib
+    from paper_1601_01237_amd.sim import Sim
+    code = {"fp32": _lib.FP32, "fp16": _lib.FP16, "bf16": _lib.BF16}[storage]
+    nz, ny, nx = shape
+    sim = Sim.__new__(Sim)
+    sim.shape = shape
+    sim.n = nx * ny * nz
+    sim.device = torch.device("cpu")
+    sim.pstride = int(lib.lbm_plane_stride(nx, ny, code))
+    sim.layout = (int(lib.lbm_row_block(nx, ny, code)), sim.pstride)
+    sim.state_elems = int(lib.lbm_state_elems(nx, ny, nz, code))
+    sim.row_half = int(lib.lbm_row_half(nx, code, 0))
+    x = torch.arange(nx)
+    h = sim.row_half
+    sim.x_pos = torch.where(x < h, 2 * x, 2 * (x - h) + 1) if h else x
+    return sim
+
+
+def _index(sim, a, i, x, y, z):
+    """Flat index of element (a, i, x, y, z) as the header states it."""
+    b, s = sim.layout
+    nz, ny, nx = sim.shape
+    zplane = 2 * Q * s * -(-ny // b)
+    pos = int(sim.x_pos[x])
+    return z * zplane + (y // b) * 2 * Q * s + (a * Q + i) * s + (y % b) * nx + pos
+
+
+CASES = [("fp32", (5, 9, 130)), ("fp32", (3, 2, 40)), ("fp32", (4, 12, 7)), ("fp16", (3, 7, 70)),
+         ("fp16", (2, 5, 9)), ("bf16", (3, 4, 6))]
+
+
+@pytest.mark.parametrize("storage,shape", CASES)
+def test_layout_round_trip_and_index_formula(lib, storage, shape):
+    sim = _host_sim(lib, shape, storage)
+    nz, ny, nx = shape
+    dtype = torch.float32 if storage == "fp32" else torch.int16  # exact ids either way
+    ids = torch.arange(2 * Q * sim.n, dtype=torch.int64)
+    if dtype == torch.int16:
+        ids = ids % 30000
+    f = ids.to(dtype).view(2, Q, nz, ny, nx)
+    if storage != "fp32":
+        f = f.view(torch.float16)  # 16-bit buffers are folded (the helpers key on the dtype)
+    flat = sim.to_state_layout(f)
+    assert flat.numel() == sim.state_elems
+    back = sim.from_state_layout(flat)
+    assert torch.equal(back.view(torch.int16) if storage != "fp32" else back,
+                       f.view(torch.int16) if storage != "fp32" else f)
+    rng = np.random.default_rng(0)
+    raw = flat.view(torch.int16) if storage != "fp32" else flat
+    fr = f.view(torch.int16) if storage != "fp32" else f
+    for _ in range(200):
+        a, i = int(rng.integers(2)), int(rng.integers(Q))
+        x, y, z = int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))
+        assert raw[_index(sim, a, i, x, y, z)] == fr[a, i, z, y, x]
+    live = sim.live_mask()
+    assert int(live.sum()) == 2 * Q * sim.n
+    assert bool((raw[~live] == 0).all())
+
+
+@pytest.mark.parametrize("storage,shape", CASES)
+def test_cells_gather(lib, storage, shape):
+    sim = _host_sim(lib, shape, storage)
+    nz, ny, nx = shape
+    f = torch.randn(2, Q, nz, ny, nx)
+    if storage != "fp32":
+        f = f.half()
+    flat = sim.to_state_layout(f)
+    rng = np.random.default_rng(1)
+    z = torch.as_tensor(rng.integers(nz, size=(4, 3)))
+    y = torch.as_tensor(rng.integers(ny, size=(4, 3)))
+    x = torch.as_tensor(rng.integers(nx, size=(4, 3)))
+    got = sim.cells(flat, z, y, x)
+    assert got.shape == (4, 3, 2, Q)
+    want = f[:, :, z, y, x].permute(2, 3, 0, 1)
+    assert torch.equal(got, want)
+
+
+def test_fp32_rows_are_blocked_by_four(lib):
+    """FP32 keeps four rows per block; the 16-bit forms whole planes."""
+    from paper_1601_01237_amd import _lib
+    assert lib.lbm_row_block(128, 128, _lib.FP32) == 4
+    assert lib.lbm_row_block(128, 3, _lib.FP32) == 3
+    assert lib.lbm_row_block(128, 128, _lib.FP16) == 128
+    assert lib.lbm_row_block(128, 128, _lib.BF16) == 128
