@@ -26,6 +26,25 @@ fluid x (a solid neighbour holds the constant rho_s and passes nothing back).
 Parameters: dL/dG^{ab} = sum_x g_bar^a . S^b and
 dL/dtau_a = sum_x sum_i lam*_i^a (f_i^a - E_i(rho^a, u)) / tau_a^2.
 
+With the regularized operator (Sec. 3, Eqs. 10-11, read as the
+second-order Hermite projection) the collision is
+
+    f*_i^a = E_i(rho^a, v^a) + (1 - omega_a) N_i^a,
+    N_i^a  = w_i (c_i c_i - T0 I) : Pi^a / (2 T0^2),
+    Pi^a   = sum_j c_j c_j (f_j^a - E_j(rho^a, u)).
+
+With Pi_bar^a = (1 - omega_a) sum_i lam*_i^a w_i (c_i c_i - T0 I) / (2 T0^2)
+the pullback through Pi^a is dL = Pi_bar^a : dPi^a, so the terms above keep
+their form with two substitutions: the population that multiplies
+E_j(rho^a, u) is mu_j^a = -c_j c_j : Pi_bar^a instead of
+(omega_a - 1) lam*_j^a, and the direct term of lam_k^a is c_k c_k : Pi_bar^a
+instead of (1 - omega_a) lam*_k^a.  dL/dtau_a = sum_x sum_i lam*_i^a N_i^a /
+tau_a^2.  Both operators are written below with mu:
+
+    rho_bar^a = sum_i w_i [mu_i^a P_i(u) + lam*_i^a P_i(v^a)]
+    u_bar     = sum_a rho^a sum_i w_i [mu_i^a dP_i(u) + lam*_i^a dP_i(v^a)]
+    lam_k^a   = -mu_k^a + rho_bar^a + u_bar . (c_k - u) / rho
+
 Streaming (push with bounce-back) is a permutation; its transpose reads
 lam*_i(x) = lam_i(x + c_i) when x + c_i is fluid and lam_{opp(i)}(x) otherwise.
 """
@@ -69,42 +88,68 @@ def stream_adjoint(lam, solid=None):
     return out
 
 
+def _projection_weights(lam_a, omega):
+    """mu_j = -c_j c_j : Pi_bar of the regularized operator, with
+    Pi_bar = (1 - omega) sum_i lam_i w_i (c_i c_i - T0 I) / (2 T0^2)."""
+    shape = lam_a.shape[1:]
+    pbar = np.zeros((3, 3) + shape, dtype=lam_a.dtype)
+    for i in range(Q):
+        for a in range(3):
+            for b in range(3):
+                h = C[i, a] * C[i, b] - (T0 if a == b else 0.0)
+                if h != 0.0:
+                    pbar[a, b] = pbar[a, b] + lam_a[i] * W[i] * h
+    pbar = pbar * ((1.0 - omega) / (2.0 * T0 * T0))
+    mu = np.empty_like(lam_a)
+    for j in range(Q):
+        mu[j] = -sum(C[j, a] * C[j, b] * pbar[a, b] for a in range(3) for b in range(3))
+    return mu
+
+
 def collide_adjoint(f, lam_star, p: Params, solid=None):
-    """Transpose of :func:`oracle.lbm.collide` at state ``f``.
+    """Transpose of :func:`oracle.lbm.collide` at state ``f`` (BGK or
+    regularized collision).
 
     Returns ``(lam, dG, dtau)``: lam = dL/df (same shape as f), dG a (2, 2)
     array of dL/dG^{ab} and dtau a length-2 array of dL/dtau_a.
     """
-    if p.collision != "bgk":
-        raise NotImplementedError("the adjoint is written for the BGK collision of Eq. (2)")
+    if p.collision not in ("bgk", "regularized"):
+        raise ValueError(p.collision)
     m = lbm.macroscopic(f, p, solid)
     fluid, rho_s, rho, u = m["fluid"], m["rho_s"], m["rho"], m["u"]
     shape = f.shape[2:]
     sums = [lbm.neighbour_sum(rho_s[b], fluid, p.rho_wall[b]) for b in range(2)]
     g = m["g"]
-    dtype = np.result_type(f, lam_star)
+    dtype = np.result_type(f, lam_star, np.asarray(p.tau).dtype)
 
     rho_bar = np.zeros((2,) + shape, dtype=dtype)
     u_bar = np.zeros((3,) + shape, dtype=dtype)
     g_bar = np.zeros((2, 3) + shape, dtype=dtype)
+    mu = np.zeros((2, Q) + shape, dtype=dtype)
     uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
     dtau = np.zeros(2, dtype=dtype)
     for a in range(2):
         omega = 1.0 / p.tau[a]
         v = u + g[a]
         vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2]
-        feq = lbm.equilibrium(rho_s[a], u)
+        if p.collision == "bgk":
+            mu[a] = (omega - 1.0) * lam_star[a]
+            part = f[a] - lbm.equilibrium(rho_s[a], u)        # df*/dtau = (f - E) / tau^2
+        else:
+            mu[a] = _projection_weights(lam_star[a], omega)
+            part = lbm.regularized_neq(f[a], rho_s[a], u)      # df*/dtau = N / tau^2
         for i in range(Q):
             ci = C[i]
             cu = ci[0] * u[0] + ci[1] * u[1] + ci[2] * u[2]
             cv = ci[0] * v[0] + ci[1] * v[1] + ci[2] * v[2]
             lw = lam_star[a, i] * W[i]
-            rho_bar[a] += lw * ((omega - 1.0) * _bracket(cu, uu) + _bracket(cv, vv))
+            mw = mu[a, i] * W[i]
+            rho_bar[a] += mw * _bracket(cu, uu) + lw * _bracket(cv, vv)
             dpu = _bracket_grad(ci, u)
             dpv = _bracket_grad(ci, v)
-            u_bar += rho_s[a] * lw * ((omega - 1.0) * dpu + dpv)
+            u_bar += rho_s[a] * (mw * dpu + lw * dpv)
             g_bar[a] += rho_s[a] * lw * dpv
-        dtau[a] = np.sum(np.where(fluid, lam_star[a] * (f[a] - feq), 0.0)) / p.tau[a] ** 2
+        dtau[a] = np.sum(np.where(fluid, lam_star[a] * part, 0.0)) / p.tau[a] ** 2
 
     rho_bar = np.where(fluid, rho_bar, 0.0)
     u_bar = np.where(fluid, u_bar, 0.0)
@@ -113,12 +158,11 @@ def collide_adjoint(f, lam_star, p: Params, solid=None):
 
     lam = np.zeros(f.shape, dtype=dtype)
     for a in range(2):
-        omega = 1.0 / p.tau[a]
         for k in range(Q):
             ck = C[k]
             proj = (u_bar[0] * (ck[0] - u[0]) + u_bar[1] * (ck[1] - u[1])
                     + u_bar[2] * (ck[2] - u[2])) / rho_safe
-            lam[a, k] = (1.0 - omega) * lam_star[a, k] + rho_bar[a] + proj
+            lam[a, k] = -mu[a, k] + rho_bar[a] + proj
 
     # Transpose of the Eq. (7) neighbour gather.
     dG = np.zeros((2, 2), dtype=dtype)

@@ -33,12 +33,13 @@ def _walls(shape):
     return solid
 
 
+@pytest.mark.parametrize("collision", ["bgk", "regularized"])
 @pytest.mark.parametrize("walls", [False, True])
-def test_one_step_dot_product(walls):
+def test_one_step_dot_product(walls, collision):
     shape = (5, 4, 6)
     solid = _walls(shape) if walls else None
     f = _state(shape, 1, solid)
-    p = Params(tau=(0.7, 1.3), G=((0.0, -1.4), (-0.6, 0.0)), rho_wall=(0.15, 0.35))
+    p = Params(tau=(0.7, 1.3), G=((0.0, -1.4), (-0.6, 0.0)), rho_wall=(0.15, 0.35), collision=collision)
     rng = np.random.default_rng(2)
     v = rng.normal(size=f.shape)
     w = rng.normal(size=f.shape)
@@ -52,13 +53,14 @@ def test_one_step_dot_product(walls):
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
 
 
+@pytest.mark.parametrize("collision", ["bgk", "regularized"])
 @pytest.mark.parametrize("walls", [False, True])
-def test_one_step_parameter_derivatives(walls):
+def test_one_step_parameter_derivatives(walls, collision):
     shape = (4, 5, 6)
     solid = _walls(shape) if walls else None
     f = _state(shape, 3, solid)
     tau, G = (0.8, 1.2), ((0.0, -1.3), (-0.9, 0.0))
-    p = Params(tau=tau, G=G, rho_wall=(0.1, 0.2))
+    p = Params(tau=tau, G=G, rho_wall=(0.1, 0.2), collision=collision)
     w = np.random.default_rng(4).normal(size=f.shape)
     _, dG, dtau = adjoint.step_adjoint(f, w, p, solid)
 
@@ -68,12 +70,12 @@ def test_one_step_parameter_derivatives(walls):
     for (a, b) in ((0, 1), (1, 0)):
         Gc = [list(r) for r in G]
         Gc[a][b] = G[a][b] + 1j * H_CS
-        cs = L(Params(tau=tau, G=Gc, rho_wall=p.rho_wall)).imag / H_CS
+        cs = L(Params(tau=tau, G=Gc, rho_wall=p.rho_wall, collision=collision)).imag / H_CS
         assert abs(dG[a, b] - cs) <= 1e-12 * abs(cs)
     for a in range(2):
         tc = list(tau)
         tc[a] = tau[a] + 1j * H_CS
-        cs = L(Params(tau=tuple(tc), G=G, rho_wall=p.rho_wall)).imag / H_CS
+        cs = L(Params(tau=tuple(tc), G=G, rho_wall=p.rho_wall, collision=collision)).imag / H_CS
         assert abs(dtau[a] - cs) <= 1e-12 * abs(cs)
 
 
@@ -132,3 +134,30 @@ def test_full_sweep_against_central_differences():
     fd_t = (Lt(tau + h) - Lt(tau - h)) / (2 * h)
     assert abs(dG - fd_G) <= 1e-6 * abs(fd_G)
     assert abs(dtau - fd_t) <= 1e-6 * abs(fd_t)
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_regularized_full_sweep_against_complex_step(walls):
+    """The regularized operator (Sec. 3) over a whole run, unequal tau."""
+    shape = (6, 5, 7)
+    rho0 = inputs.sphere_droplet(shape, radius=1.8, seed=11)
+    solid = None
+    if walls:
+        solid = np.zeros(shape, bool)
+        solid[0] = True
+        rho0[:, solid] = 0.0
+    target = inputs.target_ellipsoid(shape, radius=1.8, seed=12)
+    p = Params(tau=(0.7, 1.1), G=((0.0, -1.2), (-1.2, 0.0)), rho_wall=(0.0, 0.1), collision="regularized")
+    steps = 8
+    L, dG, dtau, drho0 = adjoint.loss_and_gradient(rho0, p, steps, target, solid)
+    assert L > 0
+    Gc = -1.2 + 1j * H_CS
+    cs_G = adjoint.loss(rho0, Params(tau=p.tau, G=((0.0, Gc), (Gc, 0.0)), rho_wall=p.rho_wall,
+                                     collision="regularized"), steps, target, solid).imag / H_CS
+    assert abs(dG - cs_G) <= 1e-11 * abs(cs_G)
+    v = inputs.uniform_noise(rho0.shape, seed=13)
+    if solid is not None:
+        v[:, solid] = 0.0
+    cs_r = adjoint.loss(rho0 + 1j * H_CS * v, p, steps, target, solid).imag / H_CS
+    assert abs(np.sum(drho0 * v) - cs_r) <= 1e-11 * abs(cs_r)
+
