@@ -82,17 +82,17 @@ def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1
     return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, nonfinite=diag["nonfinite"], n=n)
 
 
-def adjoint_cost(n=96, steps=20, adjoint_tile=None):
+def adjoint_cost(n=96, steps=20, adjoint_tile=None, collision="bgk"):
     """Forward step vs one reverse step on the differentiation workload (n^3, R = 20 n / 96).
 
     Both at the library's automatic tiling unless ``adjoint_tile`` names the
-    adjoint march's shape (0, 2 or 4)."""
+    adjoint march's shape (0, 2 or 4); ``collision`` is the operator of both."""
     import torch
     from paper_1601_01237_amd import inputs
     from paper_1601_01237_amd.autograd import Reverse
     from paper_1601_01237_amd.sim import Sim
     rho0 = inputs.sphere_droplet((n, n, n), radius=20.0 * n / 96.0, seed=0)
-    sim = Sim(rho0, tau=(1.0, 1.0), G=-1.0)
+    sim = Sim(rho0, tau=(1.0, 1.0), G=-1.0, collision=collision)
     fwd_ms = time_steps(sim, steps, 5)
     if adjoint_tile is not None:
         sim.set_tiling(adjoint_tile, 0)
@@ -261,6 +261,7 @@ def main():
         extra["384x192x192_walls_fp32"] = {k: round(v, 3) for k, v in r.items() if k != "n"}
         print("[bench] adjoint 96^3", file=sys.stderr, flush=True)
         extra["adjoint_96^3"] = adjoint_cost()
+        extra["adjoint_96^3_regularized"] = adjoint_cost(collision="regularized")
 
     cpu = None
     if not args.no_cpu:

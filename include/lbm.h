@@ -238,8 +238,10 @@ lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
  * diagnostics use 64x8.  Host-side setting. */
 lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t tile, int32_t zchunk);
 
-/* ---- Adjoint (reverse mode) of one step, FP32 storage and BGK only -----
- * (other storage forms or the regularized collision: LBM_ENOTSUP) 
+/* ---- Adjoint (reverse mode) of one step, FP32 storage -------------------
+ * (16-bit storage forms: LBM_ENOTSUP).  Both collision operators: BGK
+ * (Eq. 2) and the regularized one (Eqs. 10-11, read as the second-order
+ * projection of the non-equilibrium momentum flux). 
  * Let X_t be the stored state at t and L a scalar objective.  With
  * lam_{t+1} = dL/dX_{t+1} (device float, lbm_state_elems(nx, ny, nz,
  * LBM_FP32), in the layout of an FP32 stored state) this computes
@@ -251,7 +253,8 @@ lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t tile, int32_t zchunk);
  *   x_t    device, a state buffer: X_t (may be a saved copy).
  *   work   device scratch; work_bytes must be at least
  *          lbm_adjoint_work_bytes(ctx) for the current tiling (else
- *          LBM_EINVAL).
+ *          LBM_EINVAL): 44 bytes per cell, plus one FP32 state buffer with
+ *          the regularized collision, plus 24 bytes per workgroup.
  * lam_in and lam_out must not alias each other or x_t. */
 size_t lbm_adjoint_work_bytes(const lbm_ctx *ctx);
 lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *x_t, const float *lam_in,

@@ -100,11 +100,11 @@ class LBMFunction(torch.autograd.Function):
     """rho(T) = run(rho0; G, tau) with a hand-written adjoint (see module doc)."""
 
     @staticmethod
-    def forward(ctx, rho0, G, tau, steps, every=50, solid=None, rho_wall=(0.0, 0.0)):
+    def forward(ctx, rho0, G, tau, steps, every=50, solid=None, rho_wall=(0.0, 0.0), collision="bgk"):
         g = float(G)
         t = float(tau)
         sim = Sim(rho0.detach().double().cpu().numpy(), tau=(t, t), G=g, solid=solid,
-                  rho_wall=rho_wall, device=rho0.device if rho0.is_cuda else "cuda:0")
+                  rho_wall=rho_wall, device=rho0.device if rho0.is_cuda else "cuda:0", collision=collision)
         ckpts = forward_with_checkpoints(sim, int(steps), int(every))
         rho, _, _ = sim.moments()
         ctx.sim = sim
@@ -120,4 +120,4 @@ class LBMFunction(torch.autograd.Function):
         ctx.sim.close()
         dev = ctx.rho0_device
         return (drho0.to(dev), torch.tensor(dG, dtype=torch.float64, device=dev),
-                torch.tensor(dtA + dtB, dtype=torch.float64, device=dev), None, None, None, None)
+                torch.tensor(dtA + dtB, dtype=torch.float64, device=dev), None, None, None, None, None)

@@ -294,12 +294,26 @@ lbm_status lbm_set_tiling(lbm_ctx* c, int32_t tile, int32_t zchunk) {
   return LBM_OK;
 }
 
+// Workspace of one reverse step: eleven FP32 fields per cell (m, sbar); with
+// the regularized collision an FP32 state-layout array dL/df (dbar); then
+// the FP64 per-workgroup partials.  Offsets are 256-byte aligned.
+struct AdjointWork {
+  size_t dbar_off, parts_off, bytes;
+};
+
+static AdjointWork adjoint_work(const lbm_ctx* c, const Tiling& t) {
+  auto up = [](size_t b) { return ((b + 255) / 256) * 256; };
+  AdjointWork w;
+  w.dbar_off = up(static_cast<size_t>(c->g.n) * 11 * sizeof(float));
+  const size_t dbar = c->ph.regularized ? static_cast<size_t>(c->g.nz) * c->g.zstride * sizeof(float) : 0;
+  w.parts_off = w.dbar_off + up(dbar);
+  w.bytes = w.parts_off + static_cast<size_t>(t.blocks > 0 ? t.blocks : 0) * 3 * sizeof(double);
+  return w;
+}
+
 size_t lbm_adjoint_work_bytes(const lbm_ctx* c) {
   if (!c) return 0;
-  const Tiling t = adjoint_tiling(c);
-  const size_t fields = static_cast<size_t>(c->g.n) * 11 * sizeof(float);
-  const size_t parts = static_cast<size_t>(t.blocks > 0 ? t.blocks : 0) * 3 * sizeof(double);
-  return ((fields + 255) / 256) * 256 + parts;
+  return adjoint_work(c, adjoint_tiling(c)).bytes;
 }
 
 lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, float* lam_out, void* work,
@@ -308,24 +322,37 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, fl
   if (work_bytes < lbm_adjoint_work_bytes(c)) return LBM_EINVAL;
   if (lam_in == lam_out || static_cast<const void*>(lam_in) == x_t || static_cast<const void*>(lam_out) == x_t)
     return LBM_EINVAL;
-  if (c->storage != Storage::F32 || c->ph.regularized) return LBM_ENOTSUP;
+  if (c->storage != Storage::F32) return LBM_ENOTSUP;
   const Tiling t = adjoint_tiling(c);
   if (t.blocks <= 0) return LBM_ENOTSUP;
-  float* m = static_cast<float*>(work);
+  const AdjointWork w = adjoint_work(c, t);
+  char* base = static_cast<char*>(work);
+  float* m = reinterpret_cast<float*>(base);
   float* sbar = m + 5 * c->g.n;
-  const size_t fields = static_cast<size_t>(c->g.n) * 11 * sizeof(float);
-  double* parts = reinterpret_cast<double*>(static_cast<char*>(work) + ((fields + 255) / 256) * 256);
+  float* dbar = c->ph.regularized ? reinterpret_cast<float*>(base + w.dbar_off) : nullptr;
+  double* parts = reinterpret_cast<double*>(base + w.parts_off);
   MarchIO io;
   io.src = x_t;
   io.links = c->links;
   io.lam = lam_in;
   io.m = m;
   io.sbar = sbar;
+  io.dbar = dbar;
   io.partials = parts;
   hipError_t e = launch_march(Storage::F32, Mode::Adjoint, c->g, c->ph, t, io, c->stream);
   if (e == hipSuccess) e = launch_finalize(parts, t.blocks, 3, nullptr, dparams, true, c->stream);
   if (e == hipSuccess) e = launch_adjoint_gather(c->g, c->links, m, sbar, c->stream);
-  if (e == hipSuccess) e = launch_adjoint_stream(c->g, c->ph, c->links, lam_in, m, lam_out, drho0, c->stream);
+  if (e == hipSuccess) {
+    if (dbar) {
+      // The regularized march stored the whole local dL/df in dbar: the
+      // stream pass pulls it with weight 1 (omega = 0 gives 1 - omega = 1).
+      Phys unit = c->ph;
+      unit.omega[0] = unit.omega[1] = 0.0f;
+      e = launch_adjoint_stream(c->g, unit, c->links, dbar, m, lam_out, drho0, c->stream);
+    } else {
+      e = launch_adjoint_stream(c->g, c->ph, c->links, lam_in, m, lam_out, drho0, c->stream);
+    }
+  }
   return from_hip(e);
 }
 

@@ -86,6 +86,7 @@ struct MarchIO {
   const float* lam = nullptr;      // Adjoint: lam_{t+1}
   float* m = nullptr;              // Adjoint: 5 N  (a^A, a^B, b_x, b_y, b_z)
   float* sbar = nullptr;           // Adjoint: 6 N  (Sbar^A xyz, Sbar^B xyz)
+  float* dbar = nullptr;           // Adjoint, regularized: dL/df without the gather term (state layout)
 };
 
 hipError_t launch_march(Storage s, Mode mode, const Grid& g, const Phys& ph, const Tiling& t,

@@ -108,6 +108,11 @@ struct AdjointSums {
   float dtau[2];
 };
 
+//
+// With REG (regularized collision) only the E(rho^a, v^a) part is summed
+// here (om1 = 0 drops the E(rho^a, u) weights); adjoint_species_reg adds the
+// pullback through the projected flux and dL/dtau_a.
+template <bool REG = false>
 __device__ __forceinline__ void adjoint_species(int s, float dot, const float lam[Q], const Local& L,
                                                 const Phys& ph, AdjointSums& A) {
   const float* u = L.u;
@@ -119,7 +124,7 @@ __device__ __forceinline__ void adjoint_species(int s, float dot, const float la
   float cv[9];
   pair_dots(v[0], v[1], v[2], cv);
   const float om = ph.omega[s];
-  const float om1 = om - 1.0f;
+  const float om1 = REG ? 0.0f : om - 1.0f;
   const float r = L.rho[s];
   const float l0 = lam[0] * W0;
   const float pu0 = 1.0f - 1.5f * uu;
@@ -161,7 +166,74 @@ __device__ __forceinline__ void adjoint_species(int s, float dot, const float la
     A.ubar[a] += r * (om1 * (au[a] - u[a] * bu) + (av[a] - v[a] * bv));
   }
   A.rbar[s] = rb;
-  A.dtau[s] = om * om * dt;
+  A.dtau[s] = REG ? 0.0f : om * om * dt;
+}
+
+// Regularized collision (Sec. 3, Eqs. 10-11): f*_i = E_i(rho, v) + (1 - w)
+// w_i (c_i c_i - T0 I) : Pi / (2 T0^2) with Pi = sum_j c_j c_j f_j - rho (T0 I
+// + u u).  With B = sum_i lam_i w_i (c_i c_i - T0 I) / (2 T0^2) and
+// Pbar = (1 - w) B, dL = Pbar : dPi adds
+//   to dL/df_k   c_k c_k : Pbar        (pb, per pair of directions)
+//   to rho_bar  -(T0 tr Pbar + u . Pbar u)
+//   to u_bar    -2 rho Pbar u
+// and dL/dtau_a = (Pi : B) / tau^2.  pb = (xx, yy, zz, xy, xz, yz) of Pbar.
+__device__ __forceinline__ void adjoint_species_reg(int s, const float lam[Q], const float f[Q], const Local& L,
+                                                    const Phys& ph, AdjointSums& A, float pb[6]) {
+  const float ux = L.u[0], uy = L.u[1], uz = L.u[2];
+  const float r = L.rho[s];
+  float e[9], fe[9];
+  float sl = lam[0] * W0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    e[k] = (lam[2 * k + 1] + lam[2 * k + 2]) * pair_w(k);
+    fe[k] = f[2 * k + 1] + f[2 * k + 2];
+    sl += e[k];
+  }
+  const float bxx = 4.5f * ((((e[0] + e[3]) + (e[4] + e[5])) + e[6]) - T0F * sl);
+  const float byy = 4.5f * ((((e[1] + e[3]) + (e[4] + e[7])) + e[8]) - T0F * sl);
+  const float bzz = 4.5f * ((((e[2] + e[5]) + (e[6] + e[7])) + e[8]) - T0F * sl);
+  const float bxy = 4.5f * (e[3] - e[4]);
+  const float bxz = 4.5f * (e[5] - e[6]);
+  const float byz = 4.5f * (e[7] - e[8]);
+  // Pi of the forward (pre-collision populations of the cell)
+  const float rt = r * T0F;
+  const float pxx = (((fe[0] + fe[3]) + (fe[4] + fe[5])) + fe[6]) - fmaf(r * ux, ux, rt);
+  const float pyy = (((fe[1] + fe[3]) + (fe[4] + fe[7])) + fe[8]) - fmaf(r * uy, uy, rt);
+  const float pzz = (((fe[2] + fe[5]) + (fe[6] + fe[7])) + fe[8]) - fmaf(r * uz, uz, rt);
+  const float pxy = (fe[3] - fe[4]) - (r * ux) * uy;
+  const float pxz = (fe[5] - fe[6]) - (r * ux) * uz;
+  const float pyz = (fe[7] - fe[8]) - (r * uy) * uz;
+  const float om = ph.omega[s];
+  A.dtau[s] = om * om * (pxx * bxx + pyy * byy + pzz * bzz + 2.0f * (pxy * bxy + pxz * bxz + pyz * byz));
+  const float keep = 1.0f - om;
+  pb[0] = keep * bxx;
+  pb[1] = keep * byy;
+  pb[2] = keep * bzz;
+  pb[3] = keep * bxy;
+  pb[4] = keep * bxz;
+  pb[5] = keep * byz;
+  const float px = pb[0] * ux + pb[3] * uy + pb[4] * uz;  // Pbar u
+  const float py = pb[3] * ux + pb[1] * uy + pb[5] * uz;
+  const float pz = pb[4] * ux + pb[5] * uy + pb[2] * uz;
+  A.rbar[s] -= T0F * (pb[0] + pb[1] + pb[2]) + (ux * px + uy * py + uz * pz);
+  A.ubar[0] -= 2.0f * r * px;
+  A.ubar[1] -= 2.0f * r * py;
+  A.ubar[2] -= 2.0f * r * pz;
+}
+
+// c_k c_k : Pbar for pair k (both of its directions).
+__device__ __forceinline__ float pair_quad(int k, const float pb[6]) {
+  switch (k) {
+    case 0: return pb[0];
+    case 1: return pb[1];
+    case 2: return pb[2];
+    case 3: return (pb[0] + pb[1]) + 2.0f * pb[3];
+    case 4: return (pb[0] + pb[1]) - 2.0f * pb[3];
+    case 5: return (pb[0] + pb[2]) + 2.0f * pb[4];
+    case 6: return (pb[0] + pb[2]) - 2.0f * pb[4];
+    case 7: return (pb[1] + pb[2]) + 2.0f * pb[5];
+    default: return (pb[1] + pb[2]) - 2.0f * pb[5];
+  }
 }
 
 // Cell outputs once both species are in: mo = (a^A, a^B, b), sb = Sbar, and
@@ -447,6 +519,7 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
                 AdjointSums A;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) A.ubar[c] = 0.0f;
+                float pb[2][6];
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                   float lam[Q], fs[Q];
@@ -454,14 +527,43 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
                   for (int i = 0; i < Q; ++i)
                     lam[i] = buf_load<float>(rl, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
                   pull_species<S, WALLS>(rc, ppb, col, cur_links, ws[s], s, fs);
-                  float dot = lam[0] * fs[0];
+                  if constexpr (REG) {
+                    adjoint_species<true>(s, 0.0f, lam, L, ph, A);
+                    adjoint_species_reg(s, lam, fs, L, ph, A, pb[s]);
+                  } else {
+                    float dot = lam[0] * fs[0];
 #pragma unroll
-                  for (int i = 1; i < Q; ++i) dot = fmaf(lam[i], fs[i], dot);
-                  adjoint_species(s, dot, lam, L, ph, A);
+                    for (int i = 1; i < Q; ++i) dot = fmaf(lam[i], fs[i], dot);
+                    adjoint_species(s, dot, lam, L, ph, A);
+                  }
                   // keep the next species' loads below this one's arithmetic
                   __builtin_amdgcn_sched_barrier(0);
                 }
                 adjoint_finish(A, L, ph, mo, sb, acc);
+                if constexpr (REG) {
+                  // dL/df of the cell without the Eq. (7) gather term:
+                  // c_k c_k : Pbar^a + A^a + b . c_k; the stream pass pulls it
+                  // in place of lam (with weight 1) and the m fields carry
+                  // only the gather term.
+                  const __amdgpu_buffer_rsrc_t rdb = plane_rsrc<float>(io.dbar, zc, g);
+#pragma unroll
+                  for (int s = 0; s < 2; ++s) {
+                    buf_store<float>(mo[s], rdb, col_b, static_cast<uint32_t>(s * Q) * ppb);
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) {
+                      const float bc = pair_cx(k) * mo[2] + pair_cy(k) * mo[3] + pair_cz(k) * mo[4];
+                      const float base = pair_quad(k, pb[s]) + mo[s];
+                      buf_store<float>(base + bc, rdb, col_b, static_cast<uint32_t>(s * Q + 2 * k + 1) * ppb);
+                      buf_store<float>(base - bc, rdb, col_b, static_cast<uint32_t>(s * Q + 2 * k + 2) * ppb);
+                    }
+                  }
+#pragma unroll
+                  for (int c = 0; c < 5; ++c) mo[c] = 0.0f;
+                }
+              } else if constexpr (REG) {
+                const __amdgpu_buffer_rsrc_t rdb = plane_rsrc<float>(io.dbar, zc, g);
+#pragma unroll
+                for (int i = 0; i < 2 * Q; ++i) buf_store<float>(0.0f, rdb, col_b, static_cast<uint32_t>(i) * ppb);
               }
 #pragma unroll
               for (int c = 0; c < 5; ++c) io.m[c * n + cell] = mo[c];
@@ -666,6 +768,14 @@ static hipError_t launch_tile(const Grid& g, const Phys& ph, const Tiling& t, co
     // Diagnostics use one shape (tile 0).
     if (t.tile != 0) return hipErrorInvalidValue;
     return launch_shape<S, WALLS, M, 64, 8, 3>(g, ph, t, io, st);
+  } else if (ph.regularized) {
+    if (!io.dbar) return hipErrorInvalidValue;
+    switch (t.tile) {
+      case 0: return launch_shape<S, WALLS, M, 64, 8, 3, true>(g, ph, t, io, st);
+      case 2: return launch_shape<S, WALLS, M, 32, 16, 2, true>(g, ph, t, io, st);
+      case 4: return launch_shape<S, WALLS, M, 64, 4, 3, true>(g, ph, t, io, st);
+      default: return hipErrorInvalidValue;
+    }
   } else {
     switch (t.tile) {
       case 0: return launch_shape<S, WALLS, M, 64, 8, 3>(g, ph, t, io, st);

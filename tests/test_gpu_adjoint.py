@@ -30,11 +30,12 @@ def _random_state(shape, seed, solid=None):
     return f.astype(np.float32).astype(np.float64), rho
 
 
+@pytest.mark.parametrize("collision", ["bgk", "regularized"])
 @pytest.mark.parametrize("walls", [False, True])
-def test_one_adjoint_step_matches_oracle(lib, walls):
+def test_one_adjoint_step_matches_oracle(lib, walls, collision):
     from paper_1601_01237_amd.autograd import Reverse, from_adjoint_layout, to_adjoint_layout
     from paper_1601_01237_amd.sim import Sim
-    say(f"adjoint one step walls={walls}")
+    say(f"adjoint one step walls={walls} {collision}")
     shape = (7, 9, 70)
     solid = None
     if walls:
@@ -42,10 +43,10 @@ def test_one_adjoint_step_matches_oracle(lib, walls):
         solid[0] = True
         solid[3, 2:6, 10:30] = True
     f, rho = _random_state(shape, 1, solid)
-    p = olbm.Params(tau=(0.8, 1.3), G=((0.0, -1.4), (-0.6, 0.0)), rho_wall=(0.15, 0.35))
+    p = olbm.Params(tau=(0.8, 1.3), G=((0.0, -1.4), (-0.6, 0.0)), rho_wall=(0.15, 0.35), collision=collision)
     if solid is not None:
         rho[:, solid] = 0.0
-    sim = Sim(rho, tau=p.tau, G=p.G, rho_wall=p.rho_wall, solid=solid)
+    sim = Sim(rho, tau=p.tau, G=p.G, rho_wall=p.rho_wall, solid=solid, collision=collision)
     sim.set_populations(torch.from_numpy(f.astype(np.float32)))
     lam1 = np.random.default_rng(2).normal(size=f.shape)
     if solid is not None:
@@ -66,8 +67,11 @@ def test_one_adjoint_step_matches_oracle(lib, walls):
     # FP32 term carries the rounding of f - f^eq.  Bound the error by the sum
     # of magnitudes of the terms.
     m = olbm.macroscopic(f, p, solid)
-    scale_tau = [np.sum(np.abs(lam1[a] * (f[a] - olbm.equilibrium(m["rho_s"][a], m["u"])))) / p.tau[a] ** 2
-                 for a in range(2)]
+    if collision == "bgk":
+        part = [f[a] - olbm.equilibrium(m["rho_s"][a], m["u"]) for a in range(2)]
+    else:
+        part = [olbm.regularized_neq(f[a], m["rho_s"][a], m["u"]) for a in range(2)]
+    scale_tau = [np.sum(np.abs(lam1[a] * part[a])) / p.tau[a] ** 2 for a in range(2)]
     assert abs(d[0] - (dG[0, 1] + dG[1, 0])) <= 1e-4 * abs(dG[0, 1] + dG[1, 0]), (d[0], dG)
     assert abs(d[1] - dtau[0]) <= 1e-6 * scale_tau[0], (d[1], dtau, scale_tau)
     assert abs(d[2] - dtau[1]) <= 1e-6 * scale_tau[1], (d[2], dtau, scale_tau)
@@ -126,6 +130,33 @@ def test_calibration_gradient_16cube_matches_fp64_oracle(lib):
     e_r = rel_err(r0.grad.cpu().numpy(), drho0_ref)
     say(f"16^3 calibration: L {float(L.detach()):.6e} vs {L_ref:.6e}; dL/dG {float(Gt.grad):.6e} vs {dG_ref:.6e} "
         f"({e_G:.1e}); dL/dtau {float(Tt.grad):.6e} vs {dtau_ref:.6e} ({e_t:.1e}); dL/drho0 {e_r:.1e}")
+    assert abs(float(L.detach()) - L_ref) <= 1e-5 * L_ref
+    assert e_G < 1e-3 and e_t < 1e-3 and e_r < 1e-3, (e_G, e_t, e_r)
+
+
+def test_regularized_calibration_gradient_16cube_matches_fp64_oracle(lib):
+    """The differentiation workload at 16^3 with the regularized collision
+    (Sec. 3) at tau = 0.8: 200 steps, checkpoints every 50."""
+    from paper_1601_01237_amd.autograd import LBMFunction
+    say("regularized calibration gradient 16^3 x 200")
+    n, steps, every = 16, 200, 50
+    rho0, target = _calibration_inputs(n)
+    G, tau = -1.0, 0.8
+    r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
+    Gt = torch.tensor(G, dtype=torch.float64, requires_grad=True)
+    Tt = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+    rho = LBMFunction.apply(r0, Gt, Tt, steps, every, None, (0.0, 0.0), "regularized")
+    tgt = torch.tensor(target, dtype=torch.float32, device="cuda")
+    L = 0.5 * ((rho[0].double() - tgt.double()) ** 2).sum()
+    L.backward()
+
+    p = olbm.Params(tau=(tau, tau), G=((0.0, G), (G, 0.0)), collision="regularized")
+    L_ref, dG_ref, dtau_ref, drho0_ref = oadj.loss_and_gradient(rho0, p, steps, target)
+    e_G = abs(float(Gt.grad) - dG_ref) / abs(dG_ref)
+    e_t = abs(float(Tt.grad) - dtau_ref) / abs(dtau_ref)
+    e_r = rel_err(r0.grad.cpu().numpy(), drho0_ref)
+    say(f"16^3 regularized calibration: L {float(L.detach()):.6e} vs {L_ref:.6e}; dL/dG {float(Gt.grad):.6e} vs "
+        f"{dG_ref:.6e} ({e_G:.1e}); dL/dtau {float(Tt.grad):.6e} vs {dtau_ref:.6e} ({e_t:.1e}); dL/drho0 {e_r:.1e}")
     assert abs(float(L.detach()) - L_ref) <= 1e-5 * L_ref
     assert e_G < 1e-3 and e_t < 1e-3 and e_r < 1e-3, (e_G, e_t, e_r)
 
@@ -200,17 +231,18 @@ def test_calibration_gradient_full_size_against_central_differences(lib, n, step
     assert abs(ad_r - fd_r) <= 1e-2 * abs(fd_r), (ad_r, fd_r)
 
 
-def test_adjoint_step_96cube_all_cells(lib):
+@pytest.mark.parametrize("collision,tau", [("bgk", 1.0), ("regularized", 0.8)])
+def test_adjoint_step_96cube_all_cells(lib, collision, tau):
     """One reverse step of the differentiation workload at its full size
-    (96^3 droplet, R = 20, tau = 1, G = -1, automatic tiling as timed),
-    every cell against the oracle."""
+    (96^3 droplet, R = 20, G = -1, automatic tiling as timed), every cell
+    against the oracle; tau = 1 with BGK, 0.8 with the regularized collision."""
     from paper_1601_01237_amd.autograd import Reverse, from_adjoint_layout, to_adjoint_layout
     from paper_1601_01237_amd.sim import Sim
-    say("adjoint one step 96^3")
+    say(f"adjoint one step 96^3 {collision}")
     n = 96
     rho0 = inputs.sphere_droplet((n, n, n), radius=20.0, seed=0)
-    p = olbm.Params(tau=(1.0, 1.0), G=((0.0, -1.0), (-1.0, 0.0)))
-    sim = Sim(rho0, tau=p.tau, G=p.G)
+    p = olbm.Params(tau=(tau, tau), G=((0.0, -1.0), (-1.0, 0.0)), collision=collision)
+    sim = Sim(rho0, tau=p.tau, G=p.G, collision=collision)
     sim.step(20)
     f = sim.populations().cpu().numpy().astype(np.float64)   # pre-collision f at t = 20
     lam1 = np.random.default_rng(9).normal(size=f.shape).astype(np.float32)
@@ -225,8 +257,11 @@ def test_adjoint_step_96cube_all_cells(lib):
     say(f"96^3 adjoint step: lam error {e:.2e}, dG {d[0]:.6e} vs {dG[0, 1] + dG[1, 0]:.6e}")
     assert e < 1e-5, e
     m = olbm.macroscopic(f, p)
-    scale_tau = [np.sum(np.abs(lam1[a] * (f[a] - olbm.equilibrium(m["rho_s"][a], m["u"])))) / p.tau[a] ** 2
-                 for a in range(2)]
+    if collision == "bgk":
+        part = [f[a] - olbm.equilibrium(m["rho_s"][a], m["u"]) for a in range(2)]
+    else:
+        part = [olbm.regularized_neq(f[a], m["rho_s"][a], m["u"]) for a in range(2)]
+    scale_tau = [np.sum(np.abs(lam1[a] * part[a])) / p.tau[a] ** 2 for a in range(2)]
     assert abs(d[0] - (dG[0, 1] + dG[1, 0])) <= 1e-4 * abs(dG[0, 1] + dG[1, 0]), (d[0], dG)
     assert abs(d[1] - dtau[0]) <= 1e-6 * scale_tau[0]
     assert abs(d[2] - dtau[1]) <= 1e-6 * scale_tau[1]
