@@ -66,20 +66,25 @@ def time_steps(sim, steps, warmup):
 
 
 def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1.0, tile=None, zchunk=None,
-             collision="bgk"):
+             collision="bgk", tune=False):
     from paper_1601_01237_amd import inputs
     from paper_1601_01237_amd.sim import Sim
     if rho0 is None:
         rho0 = inputs.sphere_droplet(shape, radius=shape[0] / 8.0, seed=0)
     sim = Sim(rho0, tau=(tau, tau), G=G, storage=storage, solid=solid, tile=tile, zchunk=zchunk,
               collision=collision)
+    tuned = {}
+    if tune:
+        # z chunk measured on this state (restored afterwards), before the warmup
+        best, _ = sim.tune()
+        tuned = dict(zchunk=best)
     ms = time_steps(sim, steps, warmup)
     _, _, diag = sim.moments(want_fields=False)
     n = int(np.prod(shape))
     sim.close()
     mlups = n / (ms * 1e-3) / 1e6
     gbs = BYTES_PER_CELL[storage] * n / (ms * 1e-3) / 1e9
-    return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, nonfinite=diag["nonfinite"], n=n)
+    return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, nonfinite=diag["nonfinite"], n=n, **tuned)
 
 
 def adjoint_cost(n=96, steps=20, adjoint_tile=None, collision="bgk"):
@@ -255,7 +260,7 @@ def main():
         del rho_big
         print("[bench] walls 384x192x192", file=sys.stderr, flush=True)
         rho_w, solid = inputs.inclined_channel((192, 192, 384), angle_deg=30.0, radius=32.0, seed=0)
-        r = run_case((192, 192, 384), "fp32", steps_big, 5, rho0=rho_w, solid=solid, tau=0.7)
+        r = run_case((192, 192, 384), "fp32", steps_big, 5, rho0=rho_w, solid=solid, tau=0.7, tune=True)
         fluid = int((~solid).sum())
         r["mlups_fluid_only"] = fluid / (r["ms_per_step"] * 1e-3) / 1e6
         extra["384x192x192_walls_fp32"] = {k: round(v, 3) for k, v in r.items() if k != "n"}

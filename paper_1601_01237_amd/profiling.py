@@ -100,6 +100,8 @@ def cmd_run(args):
     print(f"[profiling] copied {args.copy_reps} x {n} bytes", flush=True)
     shape, kw = workload(args.workload, args.storage, args.collision)
     sim = Sim(**kw)
+    if args.zchunk:
+        sim.set_tiling(-1, args.zchunk)
     sim.step(args.steps)
     torch.cuda.synchronize()
     sim.close()
@@ -234,6 +236,7 @@ def main(argv=None):
     r.add_argument("--collision", default="bgk", choices=["bgk", "regularized"])
     r.add_argument("--copy-gib", type=float, default=2.0)
     r.add_argument("--copy-reps", type=int, default=3)
+    r.add_argument("--zchunk", type=int, default=0, help="z planes per workgroup (0 = the library's default)")
     ra = sub.add_parser("run-adjoint")
     ra.add_argument("--n", type=int, default=96)
     ra.add_argument("--steps", type=int, default=20)

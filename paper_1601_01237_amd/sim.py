@@ -117,6 +117,7 @@ class Sim:
                 C.byref(ctx), C.byref(p), _ptr(self.bufs[0]), _ptr(self.bufs[1]),
                 _ptr(self.solid_dev), _ptr(self.rho0_dev), C.c_void_p(self.stream.cuda_stream)))
         self.ctx = ctx
+        self.tiling = (-1, 0)
         if tile is not None or zchunk is not None:
             self.set_tiling(-1 if tile is None else tile, zchunk or 0)
 
@@ -170,6 +171,34 @@ class Sim:
     def set_tiling(self, tile=-1, zchunk=0):
         """Tile shape of the step kernel (-1 = automatic, 0..9, see lbm_set_tiling) and z planes per workgroup."""
         _lib.check("lbm_set_tiling", self.lib.lbm_set_tiling(self.ctx, int(tile), int(zchunk)))
+        self.tiling = (int(tile), int(zchunk))
+
+    def tune(self, zchunks=(0, 8, 12, 16, 24, 32, 48, 64), tile=-1, steps=None):
+        """Time the step at each z chunk of ``zchunks`` (0 = the library's
+        default) for tile shape ``tile`` and keep the fastest.  The state and
+        time level are restored afterwards (bitwise: every tiling computes the
+        same step), so tuning can precede any run.  Returns (best zchunk,
+        {zchunk: ms per step})."""
+        import torch
+        nz = self.shape[0]
+        cands = [z for z in dict.fromkeys(int(z) for z in zchunks) if z <= nz]
+        n = int(steps) if steps else max(2, min(20, int(4e8 // self.n)))
+        ckpt = self.checkpoint()
+        times = {}
+        for z in cands:
+            self.set_tiling(tile, z)
+            self.step(1)
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            start.record(self.stream)
+            self.step(n)
+            end.record(self.stream)
+            end.synchronize()
+            times[z] = start.elapsed_time(end) / n
+        self.restore(ckpt)
+        best = min(times, key=times.get)
+        self.set_tiling(tile, best)
+        return best, times
 
     @property
     def state(self):

@@ -267,3 +267,38 @@ def test_adjoint_step_96cube_all_cells(lib, collision, tau):
     assert abs(d[2] - dtau[1]) <= 1e-6 * scale_tau[1]
     e = rel_err(drho.view(2, n, n, n).cpu().numpy(), np.einsum("i,aizyx->azyx", olbm.W, mu))
     assert e < 1e-5, e
+
+
+def test_adjoint_workspace_size_and_checks(lib):
+    """The regularized adjoint needs one FP32 state array more workspace; a
+    workspace one byte short, aliased arrays and 16-bit storage are refused
+    before anything is launched."""
+    import ctypes
+    from paper_1601_01237_amd.sim import Sim
+    say("adjoint workspace checks")
+    shape = (6, 9, 20)
+    rho0 = inputs.sphere_droplet(shape, radius=2.5, seed=3)
+    sims = {c: Sim(rho0, tau=(0.8, 0.8), G=-1.0, collision=c) for c in ("bgk", "regularized")}
+    wb = {c: int(lib.lbm_adjoint_work_bytes(s.ctx)) for c, s in sims.items()}
+    state_bytes = sims["bgk"].state_elems * 4
+    assert wb["regularized"] - wb["bgk"] == -(-state_bytes // 256) * 256
+    s = sims["regularized"]
+    lam_in = torch.zeros(s.lam_elems, dtype=torch.float32, device="cuda")
+    lam_out = torch.zeros_like(lam_in)
+    dparams = torch.zeros(3, dtype=torch.float64, device="cuda")
+    work = torch.empty(wb["regularized"], dtype=torch.uint8, device="cuda")
+    p = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    short = ctypes.c_size_t(wb["regularized"] - 1)
+    assert lib.lbm_adjoint_step(s.ctx, p(s.state), p(lam_in), p(lam_out), p(work), short, p(dparams), None) == -1
+    full = ctypes.c_size_t(wb["regularized"])
+    assert lib.lbm_adjoint_step(s.ctx, p(s.state), p(lam_in), p(lam_in), p(work), full, p(dparams), None) == -1
+    assert lib.lbm_adjoint_step(s.ctx, p(s.state), p(lam_in), p(lam_out), p(work), full, p(dparams), None) == 0
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(lam_out).all())
+    for sim in sims.values():
+        sim.close()
+    h = Sim(rho0, storage="fp16")
+    work16 = torch.empty(int(lib.lbm_adjoint_work_bytes(h.ctx)), dtype=torch.uint8, device="cuda")
+    assert lib.lbm_adjoint_step(h.ctx, p(h.state), p(lam_in), p(lam_out), p(work16),
+                                ctypes.c_size_t(work16.numel()), p(dparams), None) == -5  # LBM_ENOTSUP
+    h.close()
