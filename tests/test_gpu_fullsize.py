@@ -87,11 +87,13 @@ def _centers(shape, solid, seed):
     return np.array(out, dtype=np.int64)
 
 
-def _sampled_step(rho0, tau, G, storage, solid=None, label="", warm=3, extra=None):
+def _sampled_step(rho0, tau, G, storage, solid=None, label="", warm=3, extra=None, tune=False):
     from paper_1601_01237_amd.sim import Sim
     shape = rho0.shape[1:]
     say(f"{label}: {storage} sampled one-step parity")
     sim = Sim(rho0, tau=(tau, tau), G=G, storage=storage, solid=solid)
+    if tune:
+        say(f"{label}: tuned z chunk {sim.tune()[0]}")
     sim.step(warm)
     centers = _centers(shape, solid, seed=7)
     if extra is not None:
@@ -166,9 +168,12 @@ def test_largest_plane_sampled_step(lib, storage, shape):
         assert err.max() <= 19 * 2.0 ** -10 * scale
 
 
-def test_walls_384x192x192_sampled_step(lib):
+@pytest.mark.parametrize("tune", [False, True])
+def test_walls_384x192x192_sampled_step(lib, tune):
+    """The walls workload at the library's default tiling and at the z chunk
+    Sim.tune picks (the configuration the benchmark times)."""
     rho0, solid = inputs.inclined_channel((192, 192, 384), angle_deg=30.0, radius=32.0, seed=0)
-    err, _, scale = _sampled_step(rho0, 0.7, -1.0, "fp32", solid=solid, label="walls 384x192x192")
+    err, _, scale = _sampled_step(rho0, 0.7, -1.0, "fp32", solid=solid, label="walls 384x192x192", tune=tune)
     assert err.max() <= 1e-6 * scale
 
 
