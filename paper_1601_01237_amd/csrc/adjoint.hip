@@ -57,29 +57,101 @@ __device__ __forceinline__ uint64_t near_pm(const Cell3& c, int s, int i, int dx
 
 // Adjoint, pass 2: A^b(x) = a^b(x) + sum_i w_i c_i . Sbar^b(x - c_i) on fluid x.
 // m holds (a^A, a^B, b_x, b_y, b_z) per cell; a^b is replaced by A^b in place.
-__global__ void __launch_bounds__(64) adjoint_gather_kernel(const Grid g, const uint32_t* __restrict__ links,
-                                                            float* __restrict__ m, const float* __restrict__ sbar) {
-  const Cell3 p = cell3(g);
-  if (!p.valid) return;
-  const uint64_t c = near(p, 0, 0, 0, g);
-  if (is_solid(links, c)) return;
-  float r[2] = {0.f, 0.f};
+// A workgroup owns BXT x ROWS columns and marches up a chunk of z planes; the
+// six Sbar fields of planes z - 1 .. z + 1 with a one-cell x-y border sit in
+// a 4-slot LDS ring, so each value is read from memory about once per
+// workgroup instead of once per neighbour.  As in the stream pass, plane
+// p_k = z0 - 1 + k lives in slot k % 4 and the loads of p_{k+2} are in
+// flight while p_k is summed.
+constexpr int SBAR_FIELDS = 6;
+
+template <int BXT, int ROWS>
+__global__ void __launch_bounds__(BXT * ROWS)
+adjoint_gather_kernel(const Grid g, const Tiling tl, const uint32_t* __restrict__ links, float* __restrict__ m,
+                      const float* __restrict__ sbar) {
+  constexpr int NT = BXT * ROWS;
+  constexpr int EX = BXT + 2, EY = ROWS + 2, PLANE = EX * EY;
+  constexpr int LPT = (PLANE + NT - 1) / NT;
+  constexpr int SLOTS = 4;
+  __shared__ float ring[SLOTS * SBAR_FIELDS * PLANE];
+
+  const int tid = threadIdx.x;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int tiles_xy = tl.tiles_x * tl.tiles_y;
+  const int bz = b / tiles_xy;
+  const int rem = b - bz * tiles_xy;
+  const int byy = rem / tl.tiles_x;
+  const int bxx = rem - byy * tl.tiles_x;
+  const int x0 = bxx * BXT, y0 = byy * ROWS, z0 = bz * tl.zchunk;
+  const int z1 = min(z0 + tl.zchunk, g.nz);
+  const int kmax = z1 - z0 + 1;  // planes p_k = z0 - 1 + k, k = 0..kmax
+  const uint32_t n = static_cast<uint32_t>(g.n);
+
+  uint32_t loff[LPT];
+  bool lhas[LPT];
 #pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const uint64_t at = near(p, -CX[i], -CY[i], -CZ[i], g);
-    const float w = weight(i);
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const float* sb = sbar + static_cast<uint64_t>(3 * s) * g.n;
-      float dot = 0.0f;
-      if (CX[i]) dot += CX[i] * sb[at];
-      if (CY[i]) dot += CY[i] * sb[g.n + at];
-      if (CZ[i]) dot += CZ[i] * sb[2 * g.n + at];
-      r[s] += w * dot;
-    }
+  for (int j = 0; j < LPT; ++j) {
+    const int l = tid + j * NT;
+    lhas[j] = l < PLANE;
+    const int ly = l / EX, lx = l - (l / EX) * EX;
+    loff[j] = static_cast<uint32_t>(wrap(y0 + ly - 1, g.ny)) * g.nx + static_cast<uint32_t>(wrap(x0 + lx - 1, g.nx));
   }
-  m[c] += r[0];
-  m[g.n + c] += r[1];
+  float fv[LPT][SBAR_FIELDS];
+  auto fetch = [&](int p) {
+    const uint32_t base = static_cast<uint32_t>(wrap(p, g.nz)) * g.nxy;
+#pragma unroll
+    for (int j = 0; j < LPT; ++j)
+#pragma unroll
+      for (int f = 0; f < SBAR_FIELDS; ++f) fv[j][f] = lhas[j] ? sbar[f * n + base + loff[j]] : 0.0f;
+  };
+  auto publish = [&](int slot) {
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+      if (!lhas[j]) continue;
+      const int l = tid + j * NT;
+#pragma unroll
+      for (int f = 0; f < SBAR_FIELDS; ++f) ring[(slot * SBAR_FIELDS + f) * PLANE + l] = fv[j][f];
+    }
+  };
+
+  const int tx = tid % BXT, ty = tid / BXT;
+  const int ex = x0 + tx, ey = y0 + ty;
+  const bool owner = ex < g.nx && ey < g.ny;
+  const uint32_t col = owner ? static_cast<uint32_t>(ey) * g.nx + static_cast<uint32_t>(ex) : 0u;
+  const int at = (ty + 1) * EX + tx + 1;
+
+  for (int k = 0; k <= 2; ++k) {
+    fetch(z0 - 1 + k);
+    publish(k);
+  }
+  __syncthreads();
+  for (int k = 1; k < kmax; ++k) {
+    if (k + 2 <= kmax) fetch(z0 + 1 + k);
+    if (owner) {
+      const uint32_t c = static_cast<uint32_t>(z0 - 1 + k) * g.nxy + col;
+      if (!is_solid(links, c)) {
+        float r[2] = {0.f, 0.f};
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          // Sbar at x - c_i: plane p_{k - c_z} (slot (k - c_z) % 4), ring cell at - c_y EX - c_x
+          const float* rs = ring + ((k - CZ[i] + SLOTS) % SLOTS) * SBAR_FIELDS * PLANE + at - CY[i] * EX - CX[i];
+          const float w = weight(i);
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            float dot = 0.0f;
+            if (CX[i]) dot += CX[i] * rs[(3 * s) * PLANE];
+            if (CY[i]) dot += CY[i] * rs[(3 * s + 1) * PLANE];
+            if (CZ[i]) dot += CZ[i] * rs[(3 * s + 2) * PLANE];
+            r[s] += w * dot;
+          }
+        }
+        m[c] += r[0];
+        m[n + c] += r[1];
+      }
+    }
+    if (k + 2 <= kmax) publish((k + 2) % SLOTS);
+    __syncthreads();
+  }
 }
 
 // dL/dX_T for L(rho(T)): lam_i(y) = grad(y + c_i), or grad(y) if y + c_i is a wall.
@@ -318,8 +390,27 @@ Tiling stream_tiling(const Grid& g, int& shape) {
 
 hipError_t launch_adjoint_gather(const Grid& g, const uint32_t* links, float* m, const float* sbar,
                                  hipStream_t st) {
-  if (g.ny > 65535 || g.nz > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(adjoint_gather_kernel, grid3(g), dim3(64), 0, st, g, links, m, sbar);
+  // The six Sbar planes are indexed with 32-bit offsets.
+  if (g.n * SBAR_FIELDS > 0xffffffffull) return hipErrorInvalidValue;
+  // The stream pass's column tiles in shorter chunks (about eight workgroups
+  // per CU): the pass is short and its chunks' first planes cost little.
+  int shape = 0;
+  Tiling t = stream_tiling(g, shape);
+  if (t.blocks <= 0) return hipErrorInvalidValue;
+  long long zc = static_cast<long long>(g.nz) * t.tiles_x * t.tiles_y / 2048;
+  if (zc < 4) zc = 4;
+  if (zc > 32) zc = 32;
+  if (zc > g.nz) zc = g.nz;
+  t.zchunk = static_cast<int>(zc);
+  t.tiles_z = (g.nz + t.zchunk - 1) / t.zchunk;
+  const long long nb = static_cast<long long>(t.tiles_x) * t.tiles_y * t.tiles_z;
+  if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+  t.blocks = static_cast<int>(nb);
+  const dim3 gr(static_cast<unsigned>(t.blocks)), bl(256);
+  if (shape == 0)
+    hipLaunchKernelGGL((adjoint_gather_kernel<64, 4>), gr, bl, 0, st, g, t, links, m, sbar);
+  else
+    hipLaunchKernelGGL((adjoint_gather_kernel<32, 8>), gr, bl, 0, st, g, t, links, m, sbar);
   return hipGetLastError();
 }
 
