@@ -186,9 +186,18 @@ __global__ void __launch_bounds__(64) adjoint_seed_kernel(const Grid g, const ui
 // p_{k+2} are in flight.  Plane p_k = z0 - 1 + k lives in slot k % 4; one
 // barrier ends each iteration, after which the slot written in it (p_{k+2},
 // last read in iteration k - 1) is visible.
+//
+// PAIRS (regularized collision): lam_in holds, instead of lam_{t+1}, the
+// direct term c_i c_i : Pbar of dL/df_i, the same for both directions of a
+// pair, in the rows of the pair's first direction (2k + 1); the rest
+// direction's term is zero.  The kernel then runs with weight 1 (omega = 0).
 constexpr int FIELDS = 5;
 
-template <int BXT, int ROWS, bool WALLS>
+// Row of lam_in read for direction i (PAIRS: the pair's first direction).
+template <bool PAIRS>
+__device__ __forceinline__ constexpr int direct_row(int i) { return PAIRS ? ((i - 1) | 1) : i; }
+
+template <int BXT, int ROWS, bool WALLS, bool PAIRS>
 __global__ void __launch_bounds__(BXT * ROWS)
 adjoint_stream_kernel(const Grid g, const Phys ph, const Tiling tl, const uint32_t* __restrict__ links,
                       const float* __restrict__ lam_in, const float* __restrict__ m, float* __restrict__ lam_out,
@@ -263,14 +272,21 @@ adjoint_stream_kernel(const Grid g, const Phys ph, const Tiling tl, const uint32
     for (int s = 0; s < 2; ++s) {
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
+        if (PAIRS && i == 0) {
+          dst[s][0] = 0.0f;
+          continue;
+        }
         const uint32_t fwd_off = col.y[1 + CY[i]] + col.x[1 + CX[i]];
+        const int row = direct_row<PAIRS>(i);
+        // after a bounce the source is opp(i) at the cell itself (same pair)
+        const int brow = PAIRS ? row : opp(i);
         if constexpr (WALLS) {
           if (i != 0 && ((lk >> opp(i)) & 1u))
-            dst[s][i] = buf_load<float, LOAD_BOUNCE>(rz[1], col_b, static_cast<uint32_t>(s * Q + opp(i)) * ppb);
+            dst[s][i] = buf_load<float, LOAD_BOUNCE>(rz[1], col_b, static_cast<uint32_t>(s * Q + brow) * ppb);
           else
-            dst[s][i] = buf_load<float>(rz[1 + CZ[i]], fwd_off, static_cast<uint32_t>(s * Q + i) * ppb);
+            dst[s][i] = buf_load<float>(rz[1 + CZ[i]], fwd_off, static_cast<uint32_t>(s * Q + row) * ppb);
         } else {
-          dst[s][i] = buf_load<float>(rz[1 + CZ[i]], fwd_off, static_cast<uint32_t>(s * Q + i) * ppb);
+          dst[s][i] = buf_load<float>(rz[1 + CZ[i]], fwd_off, static_cast<uint32_t>(s * Q + row) * ppb);
         }
       }
     }
@@ -324,8 +340,8 @@ adjoint_stream_kernel(const Grid g, const Phys ph, const Tiling tl, const uint32
             const __amdgpu_buffer_rsrc_t rc = plane_rsrc<float>(lam_in, zc, g);
             float acc = 0.0f;
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
-              acc += weight(i) * buf_load<float>(rc, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
+            for (int i = PAIRS ? 1 : 0; i < Q; ++i)
+              acc += weight(i) * buf_load<float>(rc, col_b, static_cast<uint32_t>(s * Q + direct_row<PAIRS>(i)) * ppb);
             d = static_cast<double>(keep[s] * acc + rp[1][s * PLANE + at]);
           }
           drho0[s * g.n + cell] = d;
@@ -414,29 +430,40 @@ hipError_t launch_adjoint_gather(const Grid& g, const uint32_t* links, float* m,
   return hipGetLastError();
 }
 
+template <bool PAIRS>
+static void launch_stream_variant(int shape, const dim3& gr, const Grid& g, const Phys& ph, const Tiling& t,
+                                  const uint32_t* links, const float* lam_in, const float* m, float* lam_out,
+                                  double* drho0, hipStream_t st) {
+  const dim3 bl(256);
+  if (shape == 0) {
+    if (links)
+      hipLaunchKernelGGL((adjoint_stream_kernel<64, 4, true, PAIRS>), gr, bl, 0, st, g, ph, t, links, lam_in, m,
+                         lam_out, drho0);
+    else
+      hipLaunchKernelGGL((adjoint_stream_kernel<64, 4, false, PAIRS>), gr, bl, 0, st, g, ph, t, links, lam_in, m,
+                         lam_out, drho0);
+  } else {
+    if (links)
+      hipLaunchKernelGGL((adjoint_stream_kernel<32, 8, true, PAIRS>), gr, bl, 0, st, g, ph, t, links, lam_in, m,
+                         lam_out, drho0);
+    else
+      hipLaunchKernelGGL((adjoint_stream_kernel<32, 8, false, PAIRS>), gr, bl, 0, st, g, ph, t, links, lam_in, m,
+                         lam_out, drho0);
+  }
+}
+
 hipError_t launch_adjoint_stream(const Grid& g, const Phys& ph, const uint32_t* links, const float* lam_in,
-                                 const float* m, float* lam_out, double* drho0, hipStream_t st) {
+                                 const float* m, float* lam_out, double* drho0, bool pairs, hipStream_t st) {
   // The five field planes are indexed with 32-bit offsets.
   if (g.n * FIELDS > 0xffffffffull) return hipErrorInvalidValue;
   int shape = 0;
   const Tiling t = stream_tiling(g, shape);
   if (t.blocks <= 0) return hipErrorInvalidValue;
-  const dim3 gr(static_cast<unsigned>(t.blocks)), bl(256);
-  if (shape == 0) {
-    if (links)
-      hipLaunchKernelGGL((adjoint_stream_kernel<64, 4, true>), gr, bl, 0, st, g, ph, t, links, lam_in, m, lam_out,
-                         drho0);
-    else
-      hipLaunchKernelGGL((adjoint_stream_kernel<64, 4, false>), gr, bl, 0, st, g, ph, t, links, lam_in, m, lam_out,
-                         drho0);
-  } else {
-    if (links)
-      hipLaunchKernelGGL((adjoint_stream_kernel<32, 8, true>), gr, bl, 0, st, g, ph, t, links, lam_in, m, lam_out,
-                         drho0);
-    else
-      hipLaunchKernelGGL((adjoint_stream_kernel<32, 8, false>), gr, bl, 0, st, g, ph, t, links, lam_in, m, lam_out,
-                         drho0);
-  }
+  const dim3 gr(static_cast<unsigned>(t.blocks));
+  if (pairs)
+    launch_stream_variant<true>(shape, gr, g, ph, t, links, lam_in, m, lam_out, drho0, st);
+  else
+    launch_stream_variant<false>(shape, gr, g, ph, t, links, lam_in, m, lam_out, drho0, st);
   return hipGetLastError();
 }
 

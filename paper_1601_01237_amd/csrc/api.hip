@@ -344,13 +344,14 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, fl
   if (e == hipSuccess) e = launch_adjoint_gather(c->g, c->links, m, sbar, c->stream);
   if (e == hipSuccess) {
     if (dbar) {
-      // The regularized march stored the whole local dL/df in dbar: the
-      // stream pass pulls it with weight 1 (omega = 0 gives 1 - omega = 1).
+      // The regularized march stored the direct term c_k c_k : Pbar of each
+      // pair in dbar: the stream pass pulls it in place of lam with weight 1
+      // (omega = 0 gives 1 - omega = 1).
       Phys unit = c->ph;
       unit.omega[0] = unit.omega[1] = 0.0f;
-      e = launch_adjoint_stream(c->g, unit, c->links, dbar, m, lam_out, drho0, c->stream);
+      e = launch_adjoint_stream(c->g, unit, c->links, dbar, m, lam_out, drho0, true, c->stream);
     } else {
-      e = launch_adjoint_stream(c->g, c->ph, c->links, lam_in, m, lam_out, drho0, c->stream);
+      e = launch_adjoint_stream(c->g, c->ph, c->links, lam_in, m, lam_out, drho0, false, c->stream);
     }
   }
   return from_hip(e);

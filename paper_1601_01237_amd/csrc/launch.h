@@ -86,7 +86,7 @@ struct MarchIO {
   const float* lam = nullptr;      // Adjoint: lam_{t+1}
   float* m = nullptr;              // Adjoint: 5 N  (a^A, a^B, b_x, b_y, b_z)
   float* sbar = nullptr;           // Adjoint: 6 N  (Sbar^A xyz, Sbar^B xyz)
-  float* dbar = nullptr;           // Adjoint, regularized: dL/df without the gather term (state layout)
+  float* dbar = nullptr;           // Adjoint, regularized: per-pair direct term of dL/df (state layout)
 };
 
 hipError_t launch_march(Storage s, Mode mode, const Grid& g, const Phys& ph, const Tiling& t,
@@ -106,9 +106,11 @@ hipError_t launch_finalize(const double* partials, int blocks, int nvals, const 
                            double* out, bool accumulate, hipStream_t st);
 hipError_t launch_adjoint_gather(const Grid& g, const uint32_t* links, float* m, const float* sbar,
                                  hipStream_t st);
+// pairs: lam_in holds the regularized collision's per-pair direct term (see
+// adjoint.hip) instead of lam_{t+1}.
 hipError_t launch_adjoint_stream(const Grid& g, const Phys& ph, const uint32_t* links,
                                  const float* lam_in, const float* m, float* lam_out,
-                                 double* drho0, hipStream_t st);
+                                 double* drho0, bool pairs, hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStream_t st);
 hipError_t launch_march_copy(Storage s, const Grid& g, const void* src, void* dst, hipStream_t st);
 hipError_t launch_adjoint_seed(const Grid& g, const uint32_t* links, const float* grad_rho,

@@ -541,29 +541,24 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
                 }
                 adjoint_finish(A, L, ph, mo, sb, acc);
                 if constexpr (REG) {
-                  // dL/df of the cell without the Eq. (7) gather term:
-                  // c_k c_k : Pbar^a + A^a + b . c_k; the stream pass pulls it
-                  // in place of lam (with weight 1) and the m fields carry
-                  // only the gather term.
+                  // The direct term c_k c_k : Pbar^a of dL/df, one value per
+                  // pair (both directions share it), in the rows of the
+                  // pair's first direction; the stream pass pulls it in place
+                  // of lam, and A, b stay in the m fields as for BGK.
                   const __amdgpu_buffer_rsrc_t rdb = plane_rsrc<float>(io.dbar, zc, g);
 #pragma unroll
-                  for (int s = 0; s < 2; ++s) {
-                    buf_store<float>(mo[s], rdb, col_b, static_cast<uint32_t>(s * Q) * ppb);
+                  for (int s = 0; s < 2; ++s)
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) {
-                      const float bc = pair_cx(k) * mo[2] + pair_cy(k) * mo[3] + pair_cz(k) * mo[4];
-                      const float base = pair_quad(k, pb[s]) + mo[s];
-                      buf_store<float>(base + bc, rdb, col_b, static_cast<uint32_t>(s * Q + 2 * k + 1) * ppb);
-                      buf_store<float>(base - bc, rdb, col_b, static_cast<uint32_t>(s * Q + 2 * k + 2) * ppb);
-                    }
-                  }
-#pragma unroll
-                  for (int c = 0; c < 5; ++c) mo[c] = 0.0f;
+                    for (int k = 0; k < 9; ++k)
+                      buf_store<float>(pair_quad(k, pb[s]), rdb, col_b, static_cast<uint32_t>(s * Q + 2 * k + 1) * ppb);
                 }
               } else if constexpr (REG) {
                 const __amdgpu_buffer_rsrc_t rdb = plane_rsrc<float>(io.dbar, zc, g);
 #pragma unroll
-                for (int i = 0; i < 2 * Q; ++i) buf_store<float>(0.0f, rdb, col_b, static_cast<uint32_t>(i) * ppb);
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                  for (int k = 0; k < 9; ++k)
+                    buf_store<float>(0.0f, rdb, col_b, static_cast<uint32_t>(s * Q + 2 * k + 1) * ppb);
               }
 #pragma unroll
               for (int c = 0; c < 5; ++c) io.m[c * n + cell] = mo[c];
