@@ -76,7 +76,7 @@ def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1
     tuned = {}
     if tune:
         # z chunk measured on this state (restored afterwards), before the warmup
-        best, _ = sim.tune()
+        _, best, _ = sim.tune()
         tuned = dict(zchunk=best)
     ms = time_steps(sim, steps, warmup)
     _, _, diag = sim.moments(want_fields=False)

@@ -679,8 +679,9 @@ Tiling make_tiling(const Grid& g, int tile, int zchunk) {
     // One workgroup fills a CU; march as many planes as leave about two
     // workgroups per CU (256 CUs) over the launch, so that the planes each
     // workgroup re-reads at the ends of its column cost little (measured at
-    // 512^3: 256 planes beat 64 by 1.5-2%).  Small grids go down to 8 planes
-    // to keep one workgroup per CU.
+    // 512^3: 256 planes beat 64 by 1.5-2%; for the paired march 512 beat 256
+    // by 1%, for the single-cell march 256 beat 512 by 1.5%).  Small grids
+    // go down to 8 planes to keep one workgroup per CU.
     const long long cols = static_cast<long long>(g.nz) * txy;
     long long zc = (cols + 511) / 512;
     if (zc < 16) {
@@ -688,7 +689,8 @@ Tiling make_tiling(const Grid& g, int tile, int zchunk) {
       if (zc < 8) zc = 8;
       if (zc > 16) zc = 16;
     }
-    if (zc > 256) zc = 256;
+    const long long cap = pair_shape(tile) ? 512 : 256;
+    if (zc > cap) zc = cap;
     if (zc > g.nz) zc = g.nz;
     zchunk = static_cast<int>(zc);
   }

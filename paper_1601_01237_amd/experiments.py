@@ -162,7 +162,7 @@ def incline_drift(shape=(192, 192, 384), angle=30.0, radius=32.0, G=G_PHYS, tau=
     nz, ny, nx = shape
     rho0, solid = inputs.inclined_channel(shape, angle_deg=angle, radius=radius, seed=0)
     sim = Sim(rho0, tau=(tau, tau), G=G, solid=solid, collision=collision)
-    zchunk, _ = sim.tune()  # the run itself is unchanged (restored bitwise)
+    _, zchunk, _ = sim.tune()  # the run itself is unchanged (restored bitwise)
     zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     zc = nz / 3.0
     region = (np.sqrt((xx - nx / 2.0) ** 2 + (yy - ny / 2.0) ** 2 + (zz - zc) ** 2) < 2.0 * radius) & ~solid

@@ -173,32 +173,40 @@ class Sim:
         _lib.check("lbm_set_tiling", self.lib.lbm_set_tiling(self.ctx, int(tile), int(zchunk)))
         self.tiling = (int(tile), int(zchunk))
 
-    def tune(self, zchunks=(0, 8, 12, 16, 24, 32, 48, 64), tile=-1, steps=None):
-        """Time the step at each z chunk of ``zchunks`` (0 = the library's
-        default) for tile shape ``tile`` and keep the fastest.  The state and
-        time level are restored afterwards (bitwise: every tiling computes the
-        same step), so tuning can precede any run.  Returns (best zchunk,
-        {zchunk: ms per step})."""
+    def tune(self, zchunks=(0, 8, 12, 16, 24, 32, 48, 64), tiles=(-1,), steps=None):
+        """Time the step for every (tile shape, z chunk) pair of ``tiles`` x
+        ``zchunks`` (tile -1 = the library's automatic shape, zchunk 0 = its
+        default chunk; see lbm_set_tiling) and keep the fastest.  The state
+        and time level are restored afterwards (bitwise: every tiling computes
+        the same step), so tuning can precede any run.  Shapes the context
+        cannot run (pair shapes on unfolded rows, for instance) are skipped.
+        Returns (tile, zchunk, {(tile, zchunk): ms per step})."""
         import torch
         nz = self.shape[0]
         cands = [z for z in dict.fromkeys(int(z) for z in zchunks) if z <= nz]
         n = int(steps) if steps else max(2, min(20, int(4e8 // self.n)))
         ckpt = self.checkpoint()
         times = {}
-        for z in cands:
-            self.set_tiling(tile, z)
-            self.step(1)
-            start = torch.cuda.Event(enable_timing=True)
-            end = torch.cuda.Event(enable_timing=True)
-            start.record(self.stream)
-            self.step(n)
-            end.record(self.stream)
-            end.synchronize()
-            times[z] = start.elapsed_time(end) / n
+        for tile in dict.fromkeys(int(t) for t in tiles):
+            for z in cands:
+                try:
+                    self.set_tiling(tile, z)
+                except _lib.LBMError:
+                    break
+                self.step(1)
+                start = torch.cuda.Event(enable_timing=True)
+                end = torch.cuda.Event(enable_timing=True)
+                start.record(self.stream)
+                self.step(n)
+                end.record(self.stream)
+                end.synchronize()
+                times[(tile, z)] = start.elapsed_time(end) / n
         self.restore(ckpt)
+        if not times:
+            raise ValueError("no tiling of the candidates runs on this grid")
         best = min(times, key=times.get)
-        self.set_tiling(tile, best)
-        return best, times
+        self.set_tiling(*best)
+        return best[0], best[1], times
 
     @property
     def state(self):

@@ -93,7 +93,7 @@ def _sampled_step(rho0, tau, G, storage, solid=None, label="", warm=3, extra=Non
     say(f"{label}: {storage} sampled one-step parity")
     sim = Sim(rho0, tau=(tau, tau), G=G, storage=storage, solid=solid)
     if tune:
-        say(f"{label}: tuned z chunk {sim.tune()[0]}")
+        say(f"{label}: tuned z chunk {sim.tune()[1]}")
     sim.step(warm)
     centers = _centers(shape, solid, seed=7)
     if extra is not None:

@@ -26,10 +26,13 @@ def test_tune_keeps_the_run_bitwise(lib, storage):
     ref.step(7)
     sim = Sim(rho0, tau=(0.8, 0.8), G=-1.0, storage=storage, solid=solid)
     sim.step(3)
-    best, times = sim.tune(zchunks=(0, 8, 16, 32, 64), steps=3)
+    tiles = (-1, 0, 2, 8) if storage == "fp16" else (-1, 0, 1, 3)
+    tile, z, times = sim.tune(zchunks=(0, 8, 16, 32, 64), tiles=tiles, steps=3)
     assert sim.t == 3
-    assert best in times and set(times) == {0, 8, 16, 32}  # 64 > nz is skipped
-    assert sim.tiling == (-1, best)
+    # 64 > nz is skipped; on folded 16-bit rows every shape runs, with walls
+    # every single-cell shape
+    assert set(times) == {(t, zc) for t in tiles for zc in (0, 8, 16, 32)}
+    assert (tile, z) in times and sim.tiling == (tile, z)
     sim.step(4)
     torch.cuda.synchronize()
     assert torch.equal(sim.state, ref.state)
