@@ -7,7 +7,9 @@
 //   stream   lam_t,i(y) = (1 - w_a) lam_{t+1},i(x) + A^a(x) + b(x) . c_i with
 //            x = y + c_i, or, when y + c_i is a wall, x = y read through
 //            direction opp(i) with the sign of c_i flipped (transpose of the
-//            pull with bounce-back, Eq. 1 and Sec. 4);
+//            pull with bounce-back, Eq. 1 and Sec. 4); with the regularized
+//            collision (Sec. 3) the first term is c_i c_i : Pbar^a(x), which
+//            the march stores per pair of directions;
 //   seed     dL/dX_T from dL/drho(T).
 
 #include "buffer.h"
