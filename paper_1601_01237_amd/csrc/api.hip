@@ -36,7 +36,7 @@ lbm_status from_hip(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; 
 // with walls, the faster of the shapes measured on each); diagnostics: shape 0.
 Tiling step_tiling(const lbm_ctx* c) {
   const int tile = c->tile >= 0 ? c->tile : auto_tile(c->g, c->links != nullptr, static_cast<int>(elem_size(c->storage)));
-  return make_tiling(c->g, tile, c->zchunk);
+  return make_tiling(c->g, tile, c->zchunk, c->links == nullptr);
 }
 Tiling aux_tiling(const lbm_ctx* c) { return make_tiling(c->g, 0, 0); }
 Tiling adjoint_tiling(const lbm_ctx* c) {

@@ -302,7 +302,7 @@ hipError_t launch_finalize(const double* partials, int blocks, int nvals, const 
 }
 
 hipError_t launch_march_copy(Storage s, const Grid& g, const void* src, void* dst, hipStream_t st) {
-  const Tiling t = make_tiling(g, 3, 0);  // 128 x 4 tiles, the default chunk of z planes
+  const Tiling t = make_tiling(g, 3, 0, true);  // 128 x 4 tiles, the open-box default chunk of z planes
   if (t.blocks <= 0) return hipErrorInvalidValue;
   if (s == Storage::F32) {
     hipLaunchKernelGGL(march_copy_kernel<float>, dim3(t.blocks), dim3(512), 0, st, g, t,

@@ -62,7 +62,9 @@ constexpr int TILE_SHAPES = 10;
 constexpr bool pair_shape(int tile) { return tile >= 6 && tile < TILE_SHAPES; }
 // Shapes the adjoint march is built for.
 constexpr bool adjoint_shape(int tile) { return tile == 0 || tile == 2 || tile == 4; }
-Tiling make_tiling(const Grid& g, int tile, int zchunk);
+// zchunk <= 0 picks a default; open_box (a step without walls) takes the
+// round-count rule of march.hip.
+Tiling make_tiling(const Grid& g, int tile, int zchunk, bool open_box = false);
 // Shape used when the caller asks for the automatic choice.
 int auto_tile(const Grid& g, bool walls, int elem_bytes);
 
