@@ -186,6 +186,21 @@ class Sim:
         cands = [z for z in dict.fromkeys(int(z) for z in zchunks) if z <= nz]
         n = int(steps) if steps else max(2, min(20, int(4e8 // self.n)))
         ckpt = self.checkpoint()
+
+        def timed(k):
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            start.record(self.stream)
+            self.step(k)
+            end.record(self.stream)
+            end.synchronize()
+            return start.elapsed_time(end)
+
+        # Bring the device to its working clocks first (about 50 ms of steps):
+        # the first candidate would otherwise pay for the ramp.
+        spent = 0.0
+        while spent < 50.0:
+            spent += timed(n)
         times = {}
         for tile in dict.fromkeys(int(t) for t in tiles):
             for z in cands:
@@ -194,13 +209,7 @@ class Sim:
                 except _lib.LBMError:
                     break
                 self.step(1)
-                start = torch.cuda.Event(enable_timing=True)
-                end = torch.cuda.Event(enable_timing=True)
-                start.record(self.stream)
-                self.step(n)
-                end.record(self.stream)
-                end.synchronize()
-                times[(tile, z)] = start.elapsed_time(end) / n
+                times[(tile, z)] = min(timed(n), timed(n)) / n  # best of two
         self.restore(ckpt)
         if not times:
             raise ValueError("no tiling of the candidates runs on this grid")
