@@ -669,8 +669,8 @@ constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
 // chunk: zchunk + 2 plane iterations (two fill the pipeline).  Take the chunk
 // length of at least 4 planes (or nz) and at most `cap` that minimises
 // rounds x iterations; the first minimum is the shortest such chunk.
-// Measured against the fixed rule below on open cubes: 64^3 47 -> 22 us,
-// 112^3 155 -> 119 us, 160^3 338 -> 286 us, 192^3 597 -> 487 us; 128^3 and
+// Measured against the fixed rule below on open cubes: 64^3 47 -> 28 us,
+// 112^3 154 -> 107 us, 160^3 332 -> 286 us, 192^3 596 -> 474 us; 128^3 and
 // 512^3 keep their chunks.
 static int round_chunk(long long txy, int nz, long long cap) {
   const int lo = nz < 4 ? nz : 4;
