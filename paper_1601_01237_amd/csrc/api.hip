@@ -35,8 +35,15 @@ lbm_status from_hip(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; 
 // Step kernel: the selected tile shape (automatic: 128x4 without walls, 64x8
 // with walls, the faster of the shapes measured on each); diagnostics: shape 0.
 Tiling step_tiling(const lbm_ctx* c) {
-  const int tile = c->tile >= 0 ? c->tile : auto_tile(c->g, c->links != nullptr, static_cast<int>(elem_size(c->storage)));
-  return make_tiling(c->g, tile, c->zchunk, c->links == nullptr);
+  const bool open_box = c->links == nullptr;
+  const int tile = c->tile >= 0 ? c->tile : auto_tile(c->g, !open_box, static_cast<int>(elem_size(c->storage)));
+  Tiling t = make_tiling(c->g, tile, c->zchunk, open_box);
+  // A small open FP32 box that would leave half the CUs idle takes 64 x 4
+  // tiles instead (twice the workgroups of 64 x 8): 18-30% faster steps
+  // measured from 16^3 to 64^3; from 72^3 on the grid fills the device.
+  if (c->tile < 0 && open_box && c->storage == Storage::F32 && t.blocks > 0 && t.blocks <= 128)
+    t = make_tiling(c->g, 4, c->zchunk, open_box);
+  return t;
 }
 Tiling aux_tiling(const lbm_ctx* c) { return make_tiling(c->g, 0, 0); }
 Tiling adjoint_tiling(const lbm_ctx* c) {
