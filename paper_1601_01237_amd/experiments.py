@@ -162,7 +162,7 @@ def incline_drift(shape=(192, 192, 384), angle=30.0, radius=32.0, G=G_PHYS, tau=
     nz, ny, nx = shape
     rho0, solid = inputs.inclined_channel(shape, angle_deg=angle, radius=radius, seed=0)
     sim = Sim(rho0, tau=(tau, tau), G=G, solid=solid, collision=collision)
-    _, zchunk, _ = sim.tune()  # the run itself is unchanged (restored bitwise)
+    tile, zchunk, _ = sim.tune(tiles=(-1, 1))  # the run itself is unchanged (restored bitwise)
     zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     zc = nz / 3.0
     region = (np.sqrt((xx - nx / 2.0) ** 2 + (yy - ny / 2.0) ** 2 + (zz - zc) ** 2) < 2.0 * radius) & ~solid
@@ -178,7 +178,7 @@ def incline_drift(shape=(192, 192, 384), angle=30.0, radius=32.0, G=G_PHYS, tau=
     fluid = int((~solid).sum())
     return dict(drift=v, drift_vec=vec.tolist(), cells=[n0, n1], droplet_volume_fraction=n1 / fluid,
                 nonfinite=d["nonfinite"], max_uf=d["max_uf"], G=G, tau=tau, steps=steps, window=window,
-                collision=collision, zchunk=zchunk)
+                collision=collision, tile=tile, zchunk=zchunk)
 
 
 def main():

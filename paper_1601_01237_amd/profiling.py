@@ -100,8 +100,8 @@ def cmd_run(args):
     print(f"[profiling] copied {args.copy_reps} x {n} bytes", flush=True)
     shape, kw = workload(args.workload, args.storage, args.collision)
     sim = Sim(**kw)
-    if args.zchunk:
-        sim.set_tiling(-1, args.zchunk)
+    if args.zchunk or args.tile >= 0:
+        sim.set_tiling(args.tile, args.zchunk)
     sim.step(args.steps)
     torch.cuda.synchronize()
     sim.close()
@@ -237,6 +237,7 @@ def main(argv=None):
     r.add_argument("--copy-gib", type=float, default=2.0)
     r.add_argument("--copy-reps", type=int, default=3)
     r.add_argument("--zchunk", type=int, default=0, help="z planes per workgroup (0 = the library's default)")
+    r.add_argument("--tile", type=int, default=-1, help="tile shape (-1 = automatic)")
     ra = sub.add_parser("run-adjoint")
     ra.add_argument("--n", type=int, default=96)
     ra.add_argument("--steps", type=int, default=20)

@@ -93,7 +93,8 @@ def _sampled_step(rho0, tau, G, storage, solid=None, label="", warm=3, extra=Non
     say(f"{label}: {storage} sampled one-step parity")
     sim = Sim(rho0, tau=(tau, tau), G=G, storage=storage, solid=solid)
     if tune:
-        say(f"{label}: tuned z chunk {sim.tune()[1]}")
+        tile, zc, _ = sim.tune(tiles=(-1, 1))  # as the benchmark's tuned cases
+        say(f"{label}: tuned tile {tile}, z chunk {zc}")
     sim.step(warm)
     centers = _centers(shape, solid, seed=7)
     if extra is not None:
@@ -170,7 +171,7 @@ def test_largest_plane_sampled_step(lib, storage, shape):
 
 @pytest.mark.parametrize("tune", [False, True])
 def test_walls_384x192x192_sampled_step(lib, tune):
-    """The walls workload at the library's default tiling and at the z chunk
+    """The walls workload at the library's default tiling and at the tiling
     Sim.tune picks (the configuration the benchmark times)."""
     rho0, solid = inputs.inclined_channel((192, 192, 384), angle_deg=30.0, radius=32.0, seed=0)
     err, _, scale = _sampled_step(rho0, 0.7, -1.0, "fp32", solid=solid, label="walls 384x192x192", tune=tune)
