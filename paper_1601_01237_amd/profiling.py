@@ -1,6 +1,6 @@
 """Counter runs and their summaries for the fused step (rocprofv3 helpers).
 
-Four subcommands:
+Five subcommands:
 
 ``run-adjoint``
     Forward then reverse steps of the differentiation workload (n^3 droplet).
@@ -18,6 +18,10 @@ Four subcommands:
     device; the step kernel's counters times that scale are its HBM bytes
     per launch.  Writes a text summary and an entry of ``profiles/traffic.json``
     tied to a hash of the kernel sources.
+
+``counters``
+    Mean per dispatch of any counters (one or more ``--pmc`` runs of ``run``)
+    for the reference copy, the pattern copy (``--march-copy``) and the step.
 
 ``stats``
     Formats the ``kernel_stats.csv`` of a ``rocprofv3 --kernel-trace --stats``
@@ -102,6 +106,14 @@ def cmd_run(args):
     sim = Sim(**kw)
     if args.zchunk or args.tile >= 0:
         sim.set_tiling(args.tile, args.zchunk)
+    if args.march_copy:
+        # the step's access pattern without arithmetic, on a copy of the state
+        dst = torch.empty_like(sim.state)
+        for _ in range(args.march_copy):
+            _lib.check("lbm_march_copy", lib.lbm_march_copy(sim.ctx, ctypes.c_void_p(sim.state.data_ptr()),
+                                                             ctypes.c_void_p(dst.data_ptr())))
+        torch.cuda.synchronize()
+        del dst
     sim.step(args.steps)
     torch.cuda.synchronize()
     sim.close()
@@ -205,6 +217,45 @@ def cmd_traffic(args):
     print("\n".join(lines))
 
 
+def _kernel_class(name):
+    if _is_copy(name):
+        return "lbm_stream_copy"
+    if "march_copy_kernel" in name:
+        return "lbm_march_copy"
+    if _is_step(name):
+        return "step"
+    return None
+
+
+def cmd_counters(args):
+    """Mean per dispatch of every counter in one or more counter_collection.csv
+    files, for the reference copy, the pattern copy and the step kernel."""
+    table = {}
+    for path in args.csv:
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                cls = _kernel_class(r["Kernel_Name"])
+                if cls is None:
+                    continue
+                key = (r["Counter_Name"], cls)
+                table.setdefault(key, []).append(float(r["Counter_Value"]))
+    counters = sorted({k[0] for k in table})
+    classes = ["lbm_stream_copy", "lbm_march_copy", "step"]
+    lines = [args.title, "", f"command: {args.command}", "",
+             f"{'counter (mean per dispatch)':32} " + " ".join(f"{c:>18}" for c in classes)]
+    for name in counters:
+        cells = []
+        for c in classes:
+            v = table.get((name, c))
+            cells.append(f"{sum(v) / len(v):18.6g}" if v else f"{'-':>18}")
+        lines.append(f"{name:32} " + " ".join(cells))
+    for note in args.note or ():
+        lines.append(note)
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def cmd_stats(args):
     with open(args.csv, newline="") as f:
         rows = list(csv.DictReader(f))
@@ -238,6 +289,8 @@ def main(argv=None):
     r.add_argument("--copy-reps", type=int, default=3)
     r.add_argument("--zchunk", type=int, default=0, help="z planes per workgroup (0 = the library's default)")
     r.add_argument("--tile", type=int, default=-1, help="tile shape (-1 = automatic)")
+    r.add_argument("--march-copy", type=int, default=0,
+                   help="launches of lbm_march_copy (the step's access pattern) before the steps")
     ra = sub.add_parser("run-adjoint")
     ra.add_argument("--n", type=int, default=96)
     ra.add_argument("--steps", type=int, default=20)
@@ -257,8 +310,15 @@ def main(argv=None):
     s.add_argument("--title", default="rocprofv3 kernel statistics")
     s.add_argument("--command", default="")
     s.add_argument("--bench", default=None)
+    k = sub.add_parser("counters")
+    k.add_argument("--csv", nargs="+", required=True)
+    k.add_argument("--out", required=True)
+    k.add_argument("--title", default="rocprofv3 counters")
+    k.add_argument("--command", default="")
+    k.add_argument("--note", action="append")
     args = ap.parse_args(argv)
-    {"run": cmd_run, "run-adjoint": cmd_run_adjoint, "traffic": cmd_traffic, "stats": cmd_stats}[args.cmd](args)
+    {"run": cmd_run, "run-adjoint": cmd_run_adjoint, "traffic": cmd_traffic, "stats": cmd_stats,
+     "counters": cmd_counters}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -109,3 +109,34 @@ def step(f, shape, tau, G, solid, rho_wall, collision="bgk"):
                 else:
                     new[s][q][cell] = fstar[s][q][src]
     return new
+
+
+def observables(f, shape, G, solid, rho_wall):
+    """Per fluid cell (rho^A, rho^B, u_F) with u_F = u + (F^A + F^B) / (2 rho)
+    (Eqs. 4-9): the mean of the mixture velocity before collision, j / rho,
+    and after the force has added F^A + F^B.  Same state format as step()."""
+    vel, w, _ = lattice()
+    nz, ny, nx = shape
+    out = {}
+    rho = {}
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                cell = (z, y, x)
+                if cell not in solid:
+                    rho[cell] = [sum(f[s][q][cell] for q in range(19)) for s in range(2)]
+    for cell, (ra, rb) in rho.items():
+        z, y, x = cell
+        j = [sum(vel[q][a] * (f[0][q][cell] + f[1][q][cell]) for q in range(19)) for a in range(3)]
+        force = [0.0, 0.0, 0.0]
+        for s in range(2):
+            other = 1 - s
+            for q in range(19):
+                c = vel[q]
+                y_ = ((z + c[2]) % nz, (y + c[1]) % ny, (x + c[0]) % nx)
+                r = rho_wall[other] if y_ in solid else rho[y_][other]
+                for a in range(3):
+                    force[a] += G[s][other] * rho[cell][s] * w[q] * c[a] * r
+        rt = ra + rb
+        out[cell] = (ra, rb, [(j[a] + 0.5 * force[a]) / rt for a in range(3)])
+    return out

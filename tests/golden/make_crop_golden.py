@@ -9,11 +9,11 @@ density per species of the crop).  Only the oracle and the seeded input
 generator are used.
 
 Stored per checkpoint step (1, 10, 100, 500, 1000, 2000) in
-``crop64_<form>.npz``: rho^A, rho^B and u_F at 8192 seeded sample cells, the
+``crop64_fp64.npz``: rho^A, rho^B and u_F at 8192 seeded sample cells, the
 maxima of |rho^A|, |rho^B| and |u_F| over the whole crop, and the oracle's
 diagnostic vector.
 
-    python tests/golden/make_crop_golden.py fp64|fp16
+    python tests/golden/make_crop_golden.py
 """
 
 import os
@@ -47,18 +47,16 @@ def sample_cells():
     return rng.integers(0, 64 ** 3, size=N_SAMPLE)
 
 
-def main(form):
+def main():
     rho0 = crop_field()
     p = lbm.Params(tau=(TAU, TAU), G=((0.0, G), (G, 0.0)))
     shift = (float(rho0[0].mean()), float(rho0[1].mean()))
     idx = sample_cells()
     f = lbm.init_state(rho0)
-    if form == "fp16":
-        f = lbm.round_storage(f, "fp16", shift)
     out = {"steps": np.array(CHECKPOINTS), "idx": idx, "rho_shift": np.array(shift)}
     t0 = time.time()
     for t in range(1, CHECKPOINTS[-1] + 1):
-        f = lbm.step(f, p) if form == "fp64" else lbm.step_stored(f, p, "fp16", shift)
+        f = lbm.step(f, p)
         if t in CHECKPOINTS:
             rho_s, uF = lbm.observables(f, p)
             flat = lambda a: a.reshape(a.shape[0], -1)[:, idx]
@@ -66,9 +64,9 @@ def main(form):
             out[f"uf_{t}"] = flat(uF)
             out[f"max_{t}"] = np.array([np.abs(rho_s[0]).max(), np.abs(rho_s[1]).max(), np.abs(uF).max()])
             out[f"diag_{t}"] = odiag.diagnostics(f, p)
-            print(f"{form} t={t} {time.time() - t0:.0f}s", flush=True)
-    np.savez_compressed(os.path.join(HERE, f"crop64_{form}.npz"), **out)
+            print(f"t={t} {time.time() - t0:.0f}s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "crop64_fp64.npz"), **out)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1])
+    main()

@@ -60,3 +60,96 @@ def test_divergent_run_is_flagged():
                     flagged = t
                     break
         assert (flagged is not None) == diverges, (tau, G, flagged)
+
+
+# ---------------------------------------------------------------------------
+# Momentum and max |u_F| entries, on moving states where the force matters
+# ---------------------------------------------------------------------------
+
+def _moving_state(shape, seed):
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.2, 1.0, size=(2,) + shape)
+    u = rng.uniform(-0.05, 0.05, size=(3,) + shape)
+    f = np.stack([lbm.equilibrium(rho[a], u) for a in range(2)])
+    return f * (1.0 + 0.05 * rng.uniform(-1.0, 1.0, size=f.shape))
+
+
+def test_momentum_entry_is_the_mean_of_pre_and_post_step_momentum():
+    """Eq. (8): u_F is the mean of the mixture velocity before and after the
+    force acts.  With G^{AB} != G^{BA} the forces do not cancel over a
+    periodic box, so sum rho u_F = (sum_x j(t) + sum_x j(t+1)) / 2 differs from
+    sum_x j(t) -- a sum of rho u (no force) or of rho (u + g) fails here.
+    j is summed from raw populations only; equal tau keeps collision from
+    changing momentum (Eq. 2)."""
+    shape = (5, 6, 7)
+    f = _moving_state(shape, seed=11)
+    p = lbm.Params(tau=(0.8, 0.8), G=((0.0, -1.7), (-0.4, 0.0)))
+    d = D.diagnostics(f, p)
+    f1 = lbm.step(f, p)
+
+    def total_j(g):
+        return np.array([np.sum(lbm.C[:, a][None, :, None, None, None] * g) for a in range(3)])
+
+    j0, j1 = total_j(f), total_j(f1)
+    want = 0.5 * (j0 + j1)
+    scale = np.abs(j1 - j0).max()
+    assert scale > 1e-3  # the force is far from cancelling
+    np.testing.assert_allclose(d[[D.MOM_X, D.MOM_Y, D.MOM_Z]], want, rtol=0, atol=1e-11 * scale)
+
+
+def test_velocity_entries_match_a_brute_force_scalar_model_with_walls():
+    """sum rho u_F and max |u_F| against tests/_scalar_lbm.observables: own
+    loops over cells and directions, wall potential on solid neighbours."""
+    from . import _scalar_lbm
+    from .test_oracle_pins import _to_scalar
+    shape = (3, 4, 5)
+    f = _moving_state(shape, seed=5)
+    solid = np.zeros(shape, bool)
+    solid[0, :, :] = True
+    solid[1, 2, 3] = True
+    f[:, :, solid] = 0.0
+    p = lbm.Params(tau=(0.7, 1.3), G=((0.0, -1.3), (-0.9, 0.0)), rho_wall=(0.2, 0.45))
+    fs, _ = _to_scalar(f, shape)
+    obs = _scalar_lbm.observables(fs, shape, p.G, {tuple(c) for c in np.argwhere(solid)}, p.rho_wall)
+    mom = np.zeros(3)
+    speed = 0.0
+    for ra, rb, uf in obs.values():
+        mom += (ra + rb) * np.array(uf)
+        speed = max(speed, float(np.sqrt(sum(v * v for v in uf))))
+    d = D.diagnostics(f, p, solid)
+    np.testing.assert_allclose(d[[D.MOM_X, D.MOM_Y, D.MOM_Z]], mom, rtol=1e-13, atol=1e-15)
+    assert abs(d[D.MAX_UF] - speed) <= 1e-13 * speed
+    assert d[D.N_FLUID] == len(obs) == np.count_nonzero(~solid)
+
+
+# ---------------------------------------------------------------------------
+# Bulk pressure reading: mechanical balance across a flat interface
+# ---------------------------------------------------------------------------
+
+def test_bulk_pressure_is_equal_on_both_sides_of_a_relaxed_flat_interface():
+    """A flat interface at rest carries no pressure jump (Eq. 12 with
+    R -> infinity).  Summing Eq. (7) across a periodic 1-D profile telescopes,
+    so in steady state T0 rho - G T0 rho^A rho^B is the same in both bulk
+    phases.  The species masses differ, so the relaxed phases are not mirror
+    images (A-rich 0.956 / 0.0078, B-rich 0.0074 / 0.958): a pressure formula
+    with a wrong sign, a missing T0 or no interaction term is unequal by
+    3e-4 or more, against 2e-10 left after 6000 steps (tau = 1)."""
+    nx, G = 48, -2.6
+    x = np.arange(nx) + 0.5
+    s = 0.5 * (1.0 - np.tanh((np.abs(x - nx / 2) - nx / 4) / 1.5))  # 1 in the A slab
+    rho0 = np.zeros((2, 1, 1, nx))
+    rho0[0, 0, 0] = 0.03 + (1.0 - 0.03) * s
+    rho0[1, 0, 0] = 0.8 + (0.03 - 0.8) * s
+    p = lbm.Params(tau=(1.0, 1.0), G=((0.0, G), (G, 0.0)))
+    f = lbm.run(lbm.init_state(rho0), p, 6000)
+    rs = lbm.species_density(f)[:, 0, 0]
+    a, b = nx // 2, 0  # middle of the A slab, middle of the B phase
+    pr = D.pressure(rs[0], rs[1], G)
+    assert abs(pr[a] - pr[b]) < 1e-8
+    # the phases really differ: other pressure formulas do not balance
+    ideal = lbm.T0 * (rs[0] + rs[1])
+    for wrong in (ideal, ideal + G * lbm.T0 * rs[0] * rs[1], ideal - G * rs[0] * rs[1]):
+        assert abs(wrong[a] - wrong[b]) > 2e-4
+    # the diagnostic vector averages the same pressure
+    d = D.diagnostics(f, p, center=(nx / 2.0, 0.0, 0.0), r_in=2.0, r_out=nx / 2.0 - 3.0)
+    assert abs(d[D.P_IN_SUM] / d[D.N_IN] - d[D.P_OUT_SUM] / d[D.N_OUT]) < 1e-8
