@@ -13,8 +13,9 @@ benchmark cases required for engineering applications" (arXiv 1601.01237):
 * Eq. (3)  third-order equilibrium, lattice temperature T0 = 1/3;
 * Eqs. (4)-(6) species density, mixture density, mixture velocity;
 * Eq. (7)  Shan-Chen inter-component force, G^{aa} = 0 (Sec. 2);
-* Eqs. (10)-(11) regularized collision of Sec. 3 (second-order Hermite
-  projection of the non-equilibrium part, a reading: see regularized_neq);
+* Eqs. (10)-(11) regularized collision of Sec. 3 (Hermite projection of the
+  non-equilibrium part onto the momentum flux, optionally plus the energy
+  flux; a reading: see regularized_neq);
 * Eqs. (8)-(9) force velocity u_F = u + g/2 and g = sum_a g^a rho^a / rho,
   with g^a = sum_b F^{ab} / rho^a;
 * Sec. 4 pointwise (halfway) bounce-back wall and the pointwise wall
@@ -76,7 +77,7 @@ class Params:
     tau: tuple = (1.0, 1.0)                     # tau_A, tau_B  (Eq. 2)
     G: tuple = ((0.0, -1.0), (-1.0, 0.0))       # G^{ab}       (Eq. 7), G^{aa} = 0
     rho_wall: tuple = (0.0, 0.0)                # rho_s^a      (Sec. 4)
-    collision: str = "bgk"                      # "bgk" (Eq. 2) or "regularized" (Eqs. 10-11)
+    collision: str = "bgk"                      # "bgk" (Eq. 2), "regularized" or "regularized3" (Eqs. 10-11)
     extra: dict = field(default_factory=dict)
 
 
@@ -209,13 +210,37 @@ def momentum_flux_neq(f_a, rho_a, u):
     return out
 
 
-def regularized_neq(f_a, rho_a, u):
+def energy_flux_hermite():
+    """Third-order Hermite polynomials of the contracted ("energy flux")
+    third moment, H^E_{i,a} = c_{ia} (|c_i|^2 - c_{ia}^2) - 2 T0 c_{ia}, for a = x, y, z.
+
+    On D3Q19 with T0 = 1/3 the diagonal polynomial c_a^3 - 3 T0 c_a vanishes
+    identically (c_a^3 = c_a), so the full contraction of the third-order
+    Hermite tensor, sum_b H_{abb}, reduces to this sum over b != a.  Returns
+    (19, 3)."""
+    c2 = (C * C).sum(axis=1)
+    return C * (c2[:, None] - C * C) - 2.0 * T0 * C
+
+
+def regularized_neq(f_a, rho_a, u, order=2):
     """Regularized non-equilibrium part, Eq. (11): f^neq_i = Phi_i : Pi^a.
 
-    Reading of Phi (the paper delegates it to citations): the second-order
-    Hermite projection Phi_i = w_i (c_i c_i - T0 I) / (2 T0^2), which keeps
-    exactly the non-equilibrium momentum flux (the second moment) and drops
-    every higher-order non-equilibrium moment.  Returns (19, nz, ny, nx).
+    Reading of Phi (the paper delegates it to citations and states only that
+    it keeps the non-equilibrium moments up to the wanted order, the second
+    for the momentum flux and the third for the energy flux, and removes the
+    rest in Hermite space): the orthogonal projection, in the w-weighted
+    inner product of the lattice, of d = f - f^eq(rho^a, u) onto
+
+    * order 2: the second-order Hermite polynomials c c - T0 I; the
+      coefficients are Pi^a = sum_i c_i c_i d_i and the reconstruction is
+      w_i (c_i c_i - T0 I) : Pi^a / (2 T0^2);
+    * order 3: those plus the energy-flux polynomials H^E of
+      :func:`energy_flux_hermite`, with coefficients q_a = sum_i H^E_{ia} d_i
+      and the reconstruction w_i H^E_i . q / N, where N = sum_i w_i
+      (H^E_{ix})^2 is the polynomials' norm on the lattice (so the
+      projection returns q exactly).
+
+    Returns (19, nz, ny, nx).
     """
     pi = momentum_flux_neq(f_a, rho_a, u)
     trace = pi[0, 0] + pi[1, 1] + pi[2, 2]
@@ -223,6 +248,15 @@ def regularized_neq(f_a, rho_a, u):
     for i in range(Q):
         cpc = sum(C[i, a] * C[i, b] * pi[a, b] for a in range(3) for b in range(3))
         out[i] = W[i] * (cpc - T0 * trace) / (2.0 * T0 * T0)
+    if order == 3:
+        he = energy_flux_hermite()
+        norm = float(np.sum(W * he[:, 0] ** 2))
+        d = f_a - equilibrium(rho_a, u)
+        q = [np.einsum("i,izyx->zyx", he[:, a], d) for a in range(3)]
+        for i in range(Q):
+            out[i] = out[i] + W[i] * sum(he[i, a] * q[a] for a in range(3)) / norm
+    elif order != 2:
+        raise ValueError(order)
     return out
 
 
@@ -231,7 +265,8 @@ def collide(f, p: Params, solid=None):
 
     BGK (Eq. 2): f* = f - (f - f^eq) / tau + F.
     Regularized (Eqs. 10-11): f* = f^eq + (1 - 1/tau) f^neq + F with the
-    projected f^neq of :func:`regularized_neq`.
+    projected f^neq of :func:`regularized_neq` ("regularized": momentum flux
+    only; "regularized3": momentum and energy flux).
     Solid cells keep zero populations.
     """
     m = macroscopic(f, p, solid)
@@ -244,8 +279,8 @@ def collide(f, p: Params, solid=None):
         if p.collision == "bgk":
             coll = -(f[a] - feq) / p.tau[a]
             fstar[a] = np.where(fluid, f[a] + coll + force, 0.0)
-        elif p.collision == "regularized":
-            neq = regularized_neq(f[a], rho_s[a], u)
+        elif p.collision in ("regularized", "regularized3"):
+            neq = regularized_neq(f[a], rho_s[a], u, order=3 if p.collision == "regularized3" else 2)
             fstar[a] = np.where(fluid, feq + (1.0 - 1.0 / p.tau[a]) * neq + force, 0.0)
         else:
             raise ValueError(p.collision)

@@ -38,8 +38,10 @@ def step(f, shape, tau, G, solid, rho_wall, collision="bgk"):
     """One step.  ``f[s][q][(z, y, x)]`` nested lists/dicts in this module's order.
 
     ``solid`` is a set of (z, y, x) wall cells.  ``collision`` is "bgk"
-    (Eq. 2) or "regularized" (Eqs. 10-11 with the non-equilibrium part
-    replaced by its second-order Hermite component).  Returns the new state.
+    (Eq. 2), "regularized" (Eqs. 10-11 with the non-equilibrium part
+    replaced by its second-order Hermite component) or "regularized3" (that
+    plus its component along the contracted third-order polynomials, the
+    energy flux).  Returns the new state.
     """
     vel, w, opp = lattice()
     nz, ny, nx = shape
@@ -81,17 +83,29 @@ def step(f, shape, tau, G, solid, rho_wall, collision="bgk"):
             v = [u[a] + g[a] for a in range(3)]
             e_u = [feq(rho[cell][s], u, vel[q], w[q]) for q in range(19)]
             e_v = [feq(rho[cell][s], v, vel[q], w[q]) for q in range(19)]
-            if collision == "regularized":
+            if collision in ("regularized", "regularized3"):
                 # second moment of the non-equilibrium part, then its
                 # Hermite-2 reconstruction w_q (c c - T0 I) : Pi / (2 T0^2)
                 pi = [[sum(vel[q][a] * vel[q][b] * (f[s][q][cell] - e_u[q]) for q in range(19))
                        for b in range(3)] for a in range(3)]
                 trace = pi[0][0] + pi[1][1] + pi[2][2]
+                # energy flux: the contracted third-order polynomials
+                # h_a(c) = sum_{b != a} (c_a c_b^2 - T0 c_a), their lattice
+                # coefficients and their (lattice) norm
+                energy = [0.0, 0.0, 0.0]
+                hnorm = 0.0
+                if collision == "regularized3":
+                    def h(c, a):
+                        return sum(c[a] * c[b] * c[b] - T0 * c[a] for b in range(3) if b != a)
+                    energy = [sum(h(vel[q], a) * (f[s][q][cell] - e_u[q]) for q in range(19)) for a in range(3)]
+                    hnorm = sum(w[q] * h(vel[q], 0) ** 2 for q in range(19))
             for q in range(19):
                 fq = f[s][q][cell]
-                if collision == "regularized":
+                if collision in ("regularized", "regularized3"):
                     cpc = sum(vel[q][a] * vel[q][b] * pi[a][b] for a in range(3) for b in range(3))
                     neq = w[q] * (cpc - T0 * trace) / (2.0 * T0 * T0)
+                    if collision == "regularized3":
+                        neq += w[q] * sum(h(vel[q], a) * energy[a] for a in range(3)) / hnorm
                     fstar[s][q][cell] = e_u[q] + (1.0 - 1.0 / tau[s]) * neq + (e_v[q] - e_u[q])
                 else:
                     fstar[s][q][cell] = fq - (fq - e_u[q]) / tau[s] + (e_v[q] - e_u[q])
