@@ -207,6 +207,28 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
 lbm_status lbm_moments(lbm_ctx *ctx, float *rho, float *u_f, double *diag,
                        const lbm_diag_region *region);
 
+/* Workgroups of the diagnostics launch that lbm_moments_static can hold. */
+#define LBM_STATIC_BLOCKS 8192
+
+/* lbm_moments for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, launch and outputs as lbm_moments (bitwise equal).  It
+ * calls no allocating routine: its per-workgroup partial sums live in a
+ * fixed device array of the library, LBM_STATIC_BLOCKS * LBM_DIAG_LEN
+ * doubles (1 MiB) per GPU, held until the process ends; every workgroup
+ * overwrites its own partials, so nothing needs clearing between calls.
+ *   Limit: the diagnostics launch (64 x 8 column tiles, z chunks of up to
+ *   256 planes) must have at most LBM_STATIC_BLOCKS workgroups, which holds
+ *   for nx*ny up to about 4.2 million cells and nx*ny*nz up to about 10^9.
+ *   Errors: LBM_EINVAL for a NULL ctx; LBM_ENOTSUP beyond the limit;
+ *   LBM_EHIP if the array's device address could not be looked up at
+ *   lbm_init or the launch fails.
+ *   Concurrency: every call on one GPU shares that GPU's array, so calls
+ *   that overlap in time on one GPU (other streams, other contexts, other
+ *   host threads) race and must be ordered by the caller. */
+lbm_status lbm_moments_static(lbm_ctx *ctx, float *rho, float *u_f, double *diag,
+                              const lbm_diag_region *region);
+
 /* Pre-collision populations f_i^a(x, t) of the current time as FP32
  * (device, 2*19*N, index (a*19 + i)*N + c); zero on solid cells. */
 lbm_status lbm_get_populations(lbm_ctx *ctx, float *f);

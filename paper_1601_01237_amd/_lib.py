@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 Q = 19
 DIAG_LEN = 16
+STATIC_BLOCKS = 8192  # LBM_STATIC_BLOCKS
 FP32, FP16, BF16 = 0, 1, 2
 BGK, REGULARIZED = 0, 1
 EUNSTABLE = -4
@@ -62,6 +63,7 @@ def _declare(lib):
         "lbm_init": (i32, [C.POINTER(vp), C.POINTER(Params), vp, vp, vp, vp, vp]),
         "lbm_step": (i32, [vp, i64]),
         "lbm_moments": (i32, [vp, vp, vp, vp, C.POINTER(DiagRegion)]),
+        "lbm_moments_static": (i32, [vp, vp, vp, vp, C.POINTER(DiagRegion)]),
         "lbm_get_populations": (i32, [vp, vp]),
         "lbm_set_populations": (i32, [vp, vp]),
         "lbm_time": (i64, [vp]),
@@ -100,7 +102,7 @@ def check(func, code):
 
 EXPORTED = ["lbm_version", "lbm_velocity_set", "lbm_status_str", "lbm_plane_stride", "lbm_row_block",
             "lbm_state_elems", "lbm_row_half", "lbm_init", "lbm_step",
-            "lbm_moments", "lbm_get_populations", "lbm_set_populations", "lbm_time",
+            "lbm_moments", "lbm_moments_static", "lbm_get_populations", "lbm_set_populations", "lbm_time",
             "lbm_set_time", "lbm_set_tiling", "lbm_adjoint_work_bytes", "lbm_adjoint_step",
             "lbm_adjoint_seed", "lbm_stream_copy", "lbm_march_copy", "lbm_destroy"]
 

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 #include <new>
 
 #include "lbm.h"
@@ -24,7 +25,40 @@ struct lbm_ctx {
   int tile, zchunk;    // tiling of the step kernel
   double* partials;    // owned reduction scratch
   size_t partials_cap; // doubles
+  int device;          // HIP device current at lbm_init
 };
+
+// Partial sums of lbm_moments_static: a fixed array in device memory, one
+// copy per GPU, held until the process ends.  Sized for LBM_STATIC_BLOCKS
+// workgroups of 16 FP64 partials each (1 MiB).  Host code never passes the
+// name itself to a kernel (on the host it only stands for the symbol): it
+// uses the device address looked up once per device by static_partials().
+static __device__ __align__(256) double scratch[LBM_STATIC_BLOCKS * LBM_DIAG_LEN];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_ptr[MAX_DEVICES] = {};
+hipError_t scratch_err[MAX_DEVICES] = {};
+bool scratch_done[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `dev`, which must be the current device.
+// Looked up on the first call for a device (lbm_init makes that call) and
+// kept; returns null if the lookup failed.
+double* static_partials(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_done[dev]) {
+    void* ptr = nullptr;
+    scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    scratch_ptr[dev] = scratch_err[dev] == hipSuccess ? static_cast<double*>(ptr) : nullptr;
+    scratch_done[dev] = true;
+  }
+  return scratch_ptr[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -188,6 +222,15 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
   c->zchunk = 0;
   c->partials = nullptr;
   c->partials_cap = 0;
+  c->device = -1;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return LBM_EHIP;
+  }
+  // Device address of the fixed partial-sum array of lbm_moments_static on
+  // this device (looked up once per device; a failed lookup only disables
+  // that entry point).
+  (void)static_partials(c->device);
 
   hipError_t e = hipSuccess;
   if (solid) {
@@ -227,20 +270,16 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   return LBM_OK;
 }
 
-lbm_status lbm_moments(lbm_ctx* c, float* rho, float* u_f, double* diag, const lbm_diag_region* region) {
-  if (!c) return LBM_EINVAL;
-  const Tiling t = aux_tiling(c);
-  if (t.blocks <= 0) return LBM_ENOTSUP;
-  if (diag) {
-    const lbm_status s = ensure_partials(c, static_cast<size_t>(t.blocks) * 16);
-    if (s != LBM_OK) return s;
-  }
+// The diagnostics march (shape 64 x 8) and its fixed-order reduction, with
+// the per-workgroup partial sums in `partials` (t.blocks * 16 doubles).
+static lbm_status moments_launch(lbm_ctx* c, const Tiling& t, double* partials, float* rho, float* u_f,
+                                 double* diag, const lbm_diag_region* region) {
   MarchIO io;
   io.src = c->buf[c->t & 1];
   io.links = c->links;
   io.rho_out = rho;
   io.uf_out = u_f;
-  io.partials = diag ? c->partials : nullptr;
+  io.partials = partials;  // written even without diag
   Region R;
   if (region) {
     R.cx = static_cast<float>(region->center[0]);
@@ -259,19 +298,28 @@ lbm_status lbm_moments(lbm_ctx* c, float* rho, float* u_f, double* diag, const l
   }
   R.p_g = static_cast<float>(0.5 * (c->p.G[0][1] + c->p.G[1][0]));
   io.region = R;
-  if (!diag) {
-    // Partials are still written by the kernel: give it the scratch.
-    const lbm_status s = ensure_partials(c, static_cast<size_t>(t.blocks) * 16);
-    if (s != LBM_OK) return s;
-    io.partials = c->partials;
-  }
   hipError_t e = launch_march(c->storage, Mode::Moments, c->g, c->ph, t, io, c->stream);
-  if (e == hipSuccess && diag) {
-    int is_max[16] = {0};
-    is_max[LBM_DIAG_MAX_UF] = 1;
-    e = launch_finalize(c->partials, t.blocks, 16, is_max, diag, false, c->stream);
-  }
+  if (e == hipSuccess && diag) e = launch_finalize(partials, t.blocks, LBM_DIAG_LEN, LBM_DIAG_MAX_UF, diag, false, c->stream);
   return from_hip(e);
+}
+
+lbm_status lbm_moments(lbm_ctx* c, float* rho, float* u_f, double* diag, const lbm_diag_region* region) {
+  if (!c) return LBM_EINVAL;
+  const Tiling t = aux_tiling(c);
+  if (t.blocks <= 0) return LBM_ENOTSUP;
+  const lbm_status s = ensure_partials(c, static_cast<size_t>(t.blocks) * LBM_DIAG_LEN);
+  if (s != LBM_OK) return s;
+  return moments_launch(c, t, c->partials, rho, u_f, diag, region);
+}
+
+lbm_status lbm_moments_static(lbm_ctx* c, float* rho, float* u_f, double* diag, const lbm_diag_region* region) {
+  if (!c) return LBM_EINVAL;
+  // The tiling of lbm_moments, so the two give bitwise equal results.
+  const Tiling t = aux_tiling(c);
+  if (t.blocks <= 0 || t.blocks > LBM_STATIC_BLOCKS) return LBM_ENOTSUP;
+  double* partials = static_partials(c->device);
+  if (!partials) return LBM_EHIP;
+  return moments_launch(c, t, partials, rho, u_f, diag, region);
 }
 
 lbm_status lbm_get_populations(lbm_ctx* c, float* f) {
@@ -347,7 +395,7 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, fl
   io.dbar = dbar;
   io.partials = parts;
   hipError_t e = launch_march(Storage::F32, Mode::Adjoint, c->g, c->ph, t, io, c->stream);
-  if (e == hipSuccess) e = launch_finalize(parts, t.blocks, 3, nullptr, dparams, true, c->stream);
+  if (e == hipSuccess) e = launch_finalize(parts, t.blocks, 3, -1, dparams, true, c->stream);
   if (e == hipSuccess) e = launch_adjoint_gather(c->g, c->links, m, sbar, c->stream);
   if (e == hipSuccess) {
     if (dbar) {

@@ -147,14 +147,14 @@ __global__ void set_pop_kernel(const Grid g, const Phys ph, const uint32_t* __re
 }
 
 // Sum (or max) of per-workgroup partials, one value per block of threads,
-// in a fixed order so that results are bitwise reproducible.
-__global__ void finalize_kernel(const double* __restrict__ partials, int blocks, int nvals,
-                                const int* __restrict__ is_max_dev, int max_index, double* out,
-                                int accumulate) {
+// in a fixed order so that results are bitwise reproducible.  Entry
+// max_index takes the maximum (the partials it reduces are >= 0).
+__global__ void finalize_kernel(const double* __restrict__ partials, int blocks, int nvals, int max_index,
+                                double* out, int accumulate) {
   __shared__ double sh[TPB];
   const int k = blockIdx.x;
   const bool mx = (k == max_index);
-  double acc = mx ? 0.0 : 0.0;
+  double acc = 0.0;
   for (int b = threadIdx.x; b < blocks; b += TPB) {
     const double v = partials[static_cast<uint64_t>(b) * nvals + k];
     acc = mx ? fmax(acc, v) : acc + v;
@@ -167,7 +167,6 @@ __global__ void finalize_kernel(const double* __restrict__ partials, int blocks,
     __syncthreads();
   }
   if (threadIdx.x == 0) out[k] = accumulate ? out[k] + sh[0] : sh[0];
-  (void)is_max_dev;
 }
 
 // Plain streaming copy: the reference for how much read + write bandwidth
@@ -289,15 +288,10 @@ hipError_t launch_set_populations(Storage s, const Grid& g, const Phys& ph, cons
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double* partials, int blocks, int nvals, const int* is_max, double* out,
+hipError_t launch_finalize(const double* partials, int blocks, int nvals, int max_index, double* out,
                            bool accumulate, hipStream_t st) {
-  // is_max on the host: the index of the (single) max entry, or -1.
-  int max_index = -1;
-  if (is_max)
-    for (int k = 0; k < nvals; ++k)
-      if (is_max[k]) max_index = k;
-  hipLaunchKernelGGL(finalize_kernel, dim3(nvals), dim3(TPB), 0, st, partials, blocks, nvals,
-                     static_cast<const int*>(nullptr), max_index, out, accumulate ? 1 : 0);
+  hipLaunchKernelGGL(finalize_kernel, dim3(nvals), dim3(TPB), 0, st, partials, blocks, nvals, max_index, out,
+                     accumulate ? 1 : 0);
   return hipGetLastError();
 }
 

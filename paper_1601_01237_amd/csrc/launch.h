@@ -104,8 +104,10 @@ hipError_t launch_get_populations(Storage s, const Grid& g, const Phys& ph, cons
                                   const void* src, float* f, hipStream_t st);
 hipError_t launch_set_populations(Storage s, const Grid& g, const Phys& ph, const uint32_t* links,
                                   const float* f, void* dst, hipStream_t st);
-hipError_t launch_finalize(const double* partials, int blocks, int nvals, const int* is_max,
-                           double* out, bool accumulate, hipStream_t st);
+// Sums the per-workgroup partials (blocks x nvals) into out[0..nvals); entry
+// max_index (-1: none) takes the maximum instead of the sum.
+hipError_t launch_finalize(const double* partials, int blocks, int nvals, int max_index, double* out,
+                           bool accumulate, hipStream_t st);
 hipError_t launch_adjoint_gather(const Grid& g, const uint32_t* links, float* m, const float* sbar,
                                  hipStream_t st);
 // pairs: lam_in holds the regularized collision's per-pair direct term (see
