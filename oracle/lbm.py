@@ -370,14 +370,22 @@ def _round_to(dev, storage):
     raise ValueError(storage)
 
 
+# The residual of the rest population is stored times this power of two: an
+# FP16 residual (at most 2^-11 of the rest value) would otherwise fall among
+# the FP16 subnormals.
+RESIDUAL_SCALE = {"fp32": 1.0, "fp16": 2048.0, "bf16": 1.0}
+
+
 def round_storage(fstar, storage, rho_shift):
     """Pass post-collision populations through the shifted 16-bit storage form.
 
     The storage rule of this build (not the paper's): each moving population
-    is stored as round(f*_i^a - w_i rho_shift^a); the rest population is stored
-    as round(rho^a - sum_{i>0} decoded_i - w_0 rho_shift^a), so that the
-    decoded populations of a cell sum to its density up to one rounding.
-    Returns the decoded values in FP64.
+    is stored as round(f*_i^a - w_i rho_shift^a); the rest population keeps
+    the remainder e = rho^a - sum_{i>0} decoded_i - w_0 rho_shift^a in two
+    stored values, round(e) and round((e - round(e)) s) with s the residual
+    scale, and reads back as round(e) + round(...) / s, so that the decoded
+    populations of a cell sum to its density up to the rounding of that
+    residual.  Returns the decoded values in FP64.
     """
     if storage == "fp64":
         return fstar
@@ -386,7 +394,9 @@ def round_storage(fstar, storage, rho_shift):
         shift = W[:, None, None, None] * rho_shift[a]
         moving = _round_to(fstar[a, 1:] - shift[1:], storage) + shift[1:]
         rho = fstar[a].sum(axis=0)
-        rest = _round_to(rho - moving.sum(axis=0) - shift[0], storage) + shift[0]
+        e = rho - moving.sum(axis=0) - shift[0]
+        high = _round_to(e, storage)
+        rest = high + _round_to((e - high) * RESIDUAL_SCALE[storage], storage) / RESIDUAL_SCALE[storage] + shift[0]
         out[a, 1:] = moving
         out[a, 0] = rest
     return out

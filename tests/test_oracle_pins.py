@@ -430,11 +430,17 @@ def test_fp16_storage_round_trip_bound():
     # moving populations, round to nearest: at most half an fp16 ulp of the
     # stored deviation
     assert np.all(np.abs(r - fstar)[:, 1:] <= dev[:, 1:] * 2.0 ** -11 + 2.0 ** -25)
-    # rest population absorbs the others' rounding: the decoded populations
-    # sum to the density up to one rounding of the stored rest deviation
+    # rest population absorbs the others' rounding, kept as a stored value
+    # plus a stored residual: the decoded populations sum to the density up
+    # to the rounding of that residual, itself at most half an ulp of half an
+    # ulp of the rest deviation (2^-11 * 2^-11)
     rest_dev = np.abs(r[:, 0] - W[0] * np.array(shift)[:, None, None, None])
     rho = fstar.sum(axis=1)
-    assert np.all(np.abs(r.sum(axis=1) - rho) <= rest_dev * 2.0 ** -11 + 2.0 ** -25)
-    # and the rounding errors do not all point the same way: the mass error is
-    # far below the sum of the per-population bounds
-    assert np.abs(r.sum(axis=1) - rho).max() < 0.1 * (dev * 2.0 ** -11).sum(axis=1).max()
+    err = np.abs(r.sum(axis=1) - rho)
+    assert np.all(err <= rest_dev * 2.0 ** -21 + 1e-15)
+    # far below a single rounding of the rest value
+    assert err.max() < 1e-3 * (rest_dev * 2.0 ** -11).max()
+    # the same for BF16 (unit roundoff 2^-8 each)
+    rb = lbm.round_storage(fstar, "bf16", shift)
+    rest_b = np.abs(rb[:, 0] - W[0] * np.array(shift)[:, None, None, None])
+    assert np.all(np.abs(rb.sum(axis=1) - rho) <= rest_b * 2.0 ** -15 + 1e-15)
