@@ -7,12 +7,15 @@ tau_A = tau_B = 1.0, third-order equilibrium, Shan-Chen G^AB = G^BA = -1.0,
 one droplet of species A with R = 16 (rho_A = 1.0 / 0.03, mirrored for B,
 +-1e-3 seeded noise), FP32 storage and arithmetic.  One step = one fused
 kernel launch updating every cell of both species.  MLUPS = cells * steps /
-seconds / 1e6.  The state lives in HBM before the timed region starts.
+seconds / 1e6.  The state lives in HBM before the timed region starts.  The
+K timed steps run back to back in 5 consecutive windows split by HIP events;
+``value`` is taken at the median per-step time over the windows (the
+windows, their spread and the mean over all K steps are printed too).
 
 Prints ONE JSON line.  ``roofline`` prices the fused kernel against HBM: 304
 algorithmic bytes per cell-step (19 populations x 2 species x 4 B, read once
-and written once) divided by the average launch duration measured with HIP
-events on the stream the kernel runs on.
+and written once) divided by the launch duration measured with HIP events on
+the stream the kernel runs on.
 """
 
 from __future__ import annotations
@@ -29,7 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_CELL = {"fp32": 304, "fp16": 152, "bf16": 152}
+BYTES_PER_CELL = {"fp32": 304, "fp16": 156, "bf16": 156}
 ALGO_BYTES_NOTE = "2 species x 19 populations x element size, read + write, per cell-step"
 
 
@@ -51,18 +54,29 @@ def stored_traffic(workload, storage):
     return ent.get("bytes_per_launch")
 
 
-def time_steps(sim, steps, warmup):
+def time_steps(sim, steps, warmup, windows=5):
+    """ms per step (= per launch) of ``steps`` steps after ``warmup`` untimed ones.
+
+    The K timed steps run back to back on the context's stream, split into
+    ``windows`` consecutive windows of (nearly) equal length with a HIP event
+    between windows (no synchronisation inside the timed region).  Returns the
+    median over the windows of the per-step time, the per-window times and the
+    mean over all K steps."""
     import torch
     sim.step(warmup)
     torch.cuda.synchronize()
     stream = sim.stream
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    sim.step(steps)
-    end.record(stream)
+    nwin = max(1, min(windows, steps))
+    sizes = [steps // nwin + (1 if k < steps % nwin else 0) for k in range(nwin)]
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(nwin + 1)]
+    events[0].record(stream)
+    for k, m in enumerate(sizes):
+        sim.step(m)
+        events[k + 1].record(stream)
     torch.cuda.synchronize()
-    return start.elapsed_time(end) / steps  # ms per step (= per launch)
+    per = [events[k].elapsed_time(events[k + 1]) / sizes[k] for k in range(nwin)]
+    total = events[0].elapsed_time(events[nwin]) / steps
+    return float(np.median(per)), per, total
 
 
 # Tile shapes the tuned cases try besides the automatic one (64 x 12 rows:
@@ -84,13 +98,14 @@ def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1
         # (restored afterwards), before the warmup
         tile, best, _ = sim.tune(tiles=TUNE_TILES)
         tuned = dict(tile=tile, zchunk=best)
-    ms = time_steps(sim, steps, warmup)
+    ms, per, mean_ms = time_steps(sim, steps, warmup)
     _, _, diag = sim.moments(want_fields=False)
     n = int(np.prod(shape))
     sim.close()
     mlups = n / (ms * 1e-3) / 1e6
     gbs = BYTES_PER_CELL[storage] * n / (ms * 1e-3) / 1e9
-    return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, nonfinite=diag["nonfinite"], n=n, **tuned)
+    return dict(ms_per_step=ms, mlups=mlups, gbs=gbs, nonfinite=diag["nonfinite"], n=n,
+                window_ms=[round(v, 5) for v in per], mean_ms_per_step=mean_ms, **tuned)
 
 
 def adjoint_cost(n=96, steps=20, adjoint_tile=None, collision="bgk"):
@@ -104,7 +119,7 @@ def adjoint_cost(n=96, steps=20, adjoint_tile=None, collision="bgk"):
     from paper_1601_01237_amd.sim import Sim
     rho0 = inputs.sphere_droplet((n, n, n), radius=20.0 * n / 96.0, seed=0)
     sim = Sim(rho0, tau=(1.0, 1.0), G=-1.0, collision=collision)
-    fwd_ms = time_steps(sim, steps, 5)
+    fwd_ms = time_steps(sim, steps, 5)[0]
     if adjoint_tile is not None:
         sim.set_tiling(adjoint_tile, 0)
     rev = Reverse(sim)
@@ -178,6 +193,10 @@ def pattern_ceiling(shape, storage="fp32", reps=20):
     sim.close()
     del dst
     return BYTES_PER_CELL[storage] * n / (ms * 1e-3) / 1e9
+
+
+def _rounded(r):
+    return {k: (v if isinstance(v, list) else round(v, 3)) for k, v in r.items() if k != "n"}
 
 
 def _lib_call(sim, src, dst):
@@ -257,19 +276,19 @@ def main():
         for storage in ("fp32", "fp16", "bf16"):
             print(f"[bench] 512^3 {storage}", file=sys.stderr, flush=True)
             r = run_case(big, storage, steps_big, 5, rho0=rho_big, tau=0.6)
-            extra[f"512^3_{storage}"] = {k: round(v, 3) for k, v in r.items() if k != "n"}
+            extra[f"512^3_{storage}"] = _rounded(r)
         extra["fp16_over_fp32_512^3"] = round(extra["512^3_fp32"]["ms_per_step"]
                                               / extra["512^3_fp16"]["ms_per_step"], 3)
         print("[bench] 512^3 fp32 regularized", file=sys.stderr, flush=True)
         r = run_case(big, "fp32", steps_big, 5, rho0=rho_big, tau=0.6, collision="regularized")
-        extra["512^3_fp32_regularized"] = {k: round(v, 3) for k, v in r.items() if k != "n"}
+        extra["512^3_fp32_regularized"] = _rounded(r)
         del rho_big
         print("[bench] walls 384x192x192", file=sys.stderr, flush=True)
         rho_w, solid = inputs.inclined_channel((192, 192, 384), angle_deg=30.0, radius=32.0, seed=0)
         r = run_case((192, 192, 384), "fp32", steps_big, 5, rho0=rho_w, solid=solid, tau=0.7, tune=True)
         fluid = int((~solid).sum())
         r["mlups_fluid_only"] = fluid / (r["ms_per_step"] * 1e-3) / 1e6
-        extra["384x192x192_walls_fp32"] = {k: round(v, 3) for k, v in r.items() if k != "n"}
+        extra["384x192x192_walls_fp32"] = _rounded(r)
         print("[bench] adjoint 96^3", file=sys.stderr, flush=True)
         extra["adjoint_96^3"] = adjoint_cost()
         extra["adjoint_96^3_regularized"] = adjoint_cost(collision="regularized")
@@ -287,6 +306,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(head["ms_per_step"], 5),
+        "timing": {"windows": len(head["window_ms"]), "window_ms_per_step": head["window_ms"],
+                   "statistic": "median over windows", "mean_ms_per_step": round(head["mean_ms_per_step"], 5),
+                   "spread": round((max(head["window_ms"]) - min(head["window_ms"])) / head["ms_per_step"], 4)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -30,10 +30,14 @@
  *             each z plane is a sequence of blocks of B = lbm_row_block(nx,
  *             ny, storage) y rows, and a block holds the B rows of population
  *             (0, 0), then those of (0, 1), ..., (1, 18), S elements apart
- *             (S = lbm_plane_stride(nx, ny, storage) >= B*nx).  Element
- *             (a, i, x, y, z) sits at index
- *               z*Z + (y / B)*38*S + (a*19 + i)*S + (y % B)*nx + pos(x),
- *             Z = 38*S*ceil(ny / B) elements per z plane.  FP32 takes B = 4
+ *             (S = lbm_plane_stride(nx, ny, storage) >= B*nx), then, in the
+ *             16-bit forms only, two residual rows: row 38 + a holds the
+ *             rounding residual r of species a's rest population, scaled by
+ *             s = 2048 (FP16) or 1 (BF16), so that the rest population reads
+ *             back as decode(X_0) + decode(r)/s.  With R = 38 rows per block
+ *             (FP32) or 40 (16-bit), element (a, i, x, y, z) sits at index
+ *               z*Z + (y / B)*R*S + (a*19 + i)*S + (y % B)*nx + pos(x),
+ *             Z = R*S*ceil(ny / B) elements per z plane.  FP32 takes B = 4
  *             (or ny if smaller): the 38 population rows a workgroup reads
  *             from one plane are one contiguous range.  The 16-bit forms
  *             take B = ny (population planes).  pos(x) = x, except for the
@@ -82,7 +86,9 @@ typedef enum {
 } lbm_status;
 
 /* Storage of the population buffers.  Arithmetic is always FP32.  The
- * 16-bit forms store X_i - w_i * rho_shift[a] rounded to nearest even. */
+ * 16-bit forms store X_i - w_i * rho_shift[a] rounded to nearest even; the
+ * rest population (i = 0), which holds most of a cell's mass, also keeps the
+ * rounding residual of that value (the residual rows of the layout). */
 typedef enum { LBM_FP32 = 0, LBM_FP16 = 1, LBM_BF16 = 2 } lbm_storage;
 
 /* Collision operator.
@@ -93,8 +99,14 @@ typedef enum { LBM_FP32 = 0, LBM_FP16 = 1, LBM_BF16 = 2 } lbm_storage;
  *                    non-equilibrium part (Pi = sum_i c_i c_i (f_i - f^eq_i))
  *                    -- a reading: the paper names the filter and takes its
  *                    formula from citations.
- * F is the exact-difference forcing term in both. */
-typedef enum { LBM_BGK = 0, LBM_REGULARIZED = 1 } lbm_collision;
+ *   LBM_REGULARIZED3 the same filter also keeping the energy flux (Sec. 3:
+ *                    the third order for the energy flux): f^neq adds
+ *                    w_i H_i . q / (2 T0^3) with the contracted third-order
+ *                    Hermite polynomials H_{i,a} = sum_{b != a} (c_a c_b^2 -
+ *                    T0 c_a) and q_a = sum_i H_{i,a} (f_i - f^eq_i).  No
+ *                    adjoint (lbm_adjoint_step answers LBM_ENOTSUP).
+ * F is the exact-difference forcing term in all three. */
+typedef enum { LBM_BGK = 0, LBM_REGULARIZED = 1, LBM_REGULARIZED3 = 2 } lbm_collision;
 
 #define LBM_Q 19
 #define LBM_DIAG_LEN 16
@@ -259,15 +271,25 @@ lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
  * chunks of 4 to 256 planes (512 for the folded shapes); with walls it is
  * about nz * tiles / 512 planes, 8 to 256.  Results do not depend on this
  * choice (bitwise).
- * The adjoint march uses the same setting when it is 0, 2 or 4, else 64x4
- * with walls and the automatic choice among 64x8 and 32x16 without;
+ * The reverse march has its own setting (lbm_set_adjoint_tiling);
  * diagnostics use 64x8.  Host-side setting. */
 lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t tile, int32_t zchunk);
 
+/* Order in which the step kernel's workgroups cover the (z chunk, tile)
+ * pairs.  The device deals consecutive workgroups to its 8 XCDs in turn and
+ * the kernel renumbers them so that each XCD (with its own L2 cache) runs a
+ * contiguous range of the order; the order therefore decides which tiles
+ * share an L2 while they run.  1 = chunk by chunk, tiles x fastest; 2 =
+ * chunk by chunk, tiles y fastest; 3 = tile by tile (x fastest), every chunk
+ * of a tile together; 4 = as 3 with tiles y fastest; 0 (the default) = 3 with
+ * walls, 1 without.  Results do not depend on this choice (bitwise).
+ * LBM_EINVAL outside 0..4.  Host-side setting. */
+lbm_status lbm_set_block_order(lbm_ctx *ctx, int32_t order);
+
 /* ---- Adjoint (reverse mode) of one step, FP32 storage -------------------
- * (16-bit storage forms: LBM_ENOTSUP).  Both collision operators: BGK
- * (Eq. 2) and the regularized one (Eqs. 10-11, read as the second-order
- * projection of the non-equilibrium momentum flux). 
+ * (16-bit storage forms and LBM_REGULARIZED3: LBM_ENOTSUP).  BGK (Eq. 2)
+ * and the regularized operator (Eqs. 10-11, read as the second-order
+ * projection of the non-equilibrium momentum flux).
  * Let X_t be the stored state at t and L a scalar objective.  With
  * lam_{t+1} = dL/dX_{t+1} (device float, lbm_state_elems(nx, ny, nz,
  * LBM_FP32), in the layout of an FP32 stored state) this computes
@@ -279,10 +301,19 @@ lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t tile, int32_t zchunk);
  *   x_t    device, a state buffer: X_t (may be a saved copy).
  *   work   device scratch; work_bytes must be at least
  *          lbm_adjoint_work_bytes(ctx) for the current tiling (else
- *          LBM_EINVAL): 44 bytes per cell, plus one FP32 state buffer with
- *          the regularized collision, plus 24 bytes per workgroup.
+ *          LBM_EINVAL): 24 bytes (three FP64 partial sums) per workgroup of
+ *          the reverse march.
  * lam_in and lam_out must not alias each other or x_t. */
 size_t lbm_adjoint_work_bytes(const lbm_ctx *ctx);
+
+/* Tiling of the reverse march (results do not depend on it, up to the
+ * summation order of dparams): shape 0 = 64x8, 1 = 32x16, 2 = 32x8, 3 = 64x4
+ * cells, or -1 (the default) for the automatic choice -- 32x8 or 64x4,
+ * whichever pads the x-y plane less; zchunk = z planes per workgroup, 0 =
+ * the default, which minimises
+ * (rounds of 256 workgroups) x (zchunk + 5).  lbm_adjoint_work_bytes follows
+ * this setting.  Host-side setting; LBM_EINVAL outside these ranges. */
+lbm_status lbm_set_adjoint_tiling(lbm_ctx *ctx, int32_t shape, int32_t zchunk);
 lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *x_t, const float *lam_in,
                             float *lam_out, void *work, size_t work_bytes,
                             double *dparams, double *drho0);

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["march.hip", "march_pair.hip", "adjoint.hip", "aux.hip", "api.hip"]
+SOURCES = ["march.hip", "march_pair.hip", "adjoint_march.hip", "adjoint.hip", "aux.hip", "api.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

@@ -26,6 +26,8 @@ struct lbm_ctx {
   double* partials;    // owned reduction scratch
   size_t partials_cap; // doubles
   int device;          // HIP device current at lbm_init
+  int adj_shape, adj_zchunk;  // tiling of the reverse march (-1 / 0: automatic)
+  int order;           // block order of the step kernel (0: automatic)
 };
 
 // Partial sums of lbm_moments_static: a fixed array in device memory, one
@@ -66,6 +68,13 @@ size_t elem_size(Storage s) { return s == Storage::F32 ? 4 : 2; }
 
 lbm_status from_hip(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; }
 
+// Automatic block order: without walls an XCD takes whole rows of tiles of
+// one z chunk (neighbouring tiles share their border rows in L2).  With walls
+// the work of a chunk depends on the geometry (solid cells are skipped), so
+// each XCD takes every chunk of a run of tiles, which keeps the XCDs evenly
+// loaded (measured: 5% on the inclined channel, 2% slower on open boxes).
+int default_order(const lbm_ctx* c) { return c->links ? ORDER_TILE_X : ORDER_PLANE_X; }
+
 // Step kernel: the selected tile shape (automatic: 128x4 without walls, 64x8
 // with walls, the faster of the shapes measured on each); diagnostics: shape 0.
 Tiling step_tiling(const lbm_ctx* c) {
@@ -77,15 +86,19 @@ Tiling step_tiling(const lbm_ctx* c) {
   // measured from 16^3 to 64^3; from 72^3 on the grid fills the device.
   if (c->tile < 0 && open_box && c->storage == Storage::F32 && t.blocks > 0 && t.blocks <= 128)
     t = make_tiling(c->g, 4, c->zchunk, open_box);
+  t.order = c->order > 0 ? c->order : default_order(c);
   return t;
 }
-Tiling aux_tiling(const lbm_ctx* c) { return make_tiling(c->g, 0, 0); }
+Tiling aux_tiling(const lbm_ctx* c) {
+  Tiling t = make_tiling(c->g, 0, 0);
+  t.order = default_order(c);
+  return t;
+}
 Tiling adjoint_tiling(const lbm_ctx* c) {
-  // With walls the adjoint march needs about 200 registers: the 64x4 shape
-  // (7 waves) holds them without spilling, the 10- and 11-wave shapes do not.
-  const int automatic = c->links ? 4 : auto_tile(c->g, true, 4);
-  const int tile = adjoint_shape(c->tile) ? c->tile : automatic;
-  return make_tiling(c->g, tile, c->tile == tile ? c->zchunk : 0);
+  const int shape = c->adj_shape >= 0 ? c->adj_shape : adjoint_auto_shape(c->g, c->links != nullptr, c->ph.regularized);
+  Tiling t = adjoint_march_tiling(c->g, shape, c->adj_zchunk);
+  t.order = default_order(c);
+  return t;
 }
 
 lbm_status ensure_partials(lbm_ctx* c, size_t need) {
@@ -189,7 +202,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
       if (!std::isfinite(p->G[a][b])) return LBM_EINVAL;
   }
   if (p->G[0][0] != 0.0 || p->G[1][1] != 0.0) return LBM_ENOTSUP;
-  if (p->collision != LBM_BGK && p->collision != LBM_REGULARIZED) return LBM_EINVAL;
+  if (p->collision != LBM_BGK && p->collision != LBM_REGULARIZED && p->collision != LBM_REGULARIZED3)
+    return LBM_EINVAL;
   const uint64_t nxy = static_cast<uint64_t>(p->nx) * p->ny;
   const uint64_t n = nxy * p->nz;
   const Storage st = static_cast<Storage>(p->storage);
@@ -209,7 +223,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
     c->ph.rho_wall[a] = static_cast<float>(p->rho_wall[a]);
     c->ph.shift[a] = st == Storage::F32 ? 0.0f : static_cast<float>(p->rho_shift[a]);
   }
-  c->ph.regularized = p->collision == LBM_REGULARIZED ? 1 : 0;
+  c->ph.regularized = p->collision == LBM_REGULARIZED3 ? 2 : (p->collision == LBM_REGULARIZED ? 1 : 0);
   c->ph.g_ab = static_cast<float>(p->G[0][1]);
   c->ph.g_ba = static_cast<float>(p->G[1][0]);
   c->storage = st;
@@ -222,6 +236,9 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
   c->zchunk = 0;
   c->partials = nullptr;
   c->partials_cap = 0;
+  c->adj_shape = -1;
+  c->adj_zchunk = 0;
+  c->order = 0;
   c->device = -1;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
@@ -349,26 +366,28 @@ lbm_status lbm_set_tiling(lbm_ctx* c, int32_t tile, int32_t zchunk) {
   return LBM_OK;
 }
 
-// Workspace of one reverse step: eleven FP32 fields per cell (m, sbar); with
-// the regularized collision an FP32 state-layout array dL/df (dbar); then
-// the FP64 per-workgroup partials.  Offsets are 256-byte aligned.
-struct AdjointWork {
-  size_t dbar_off, parts_off, bytes;
-};
+lbm_status lbm_set_block_order(lbm_ctx* c, int32_t order) {
+  if (!c || order < 0 || order > BLOCK_ORDERS) return LBM_EINVAL;
+  c->order = order;
+  return LBM_OK;
+}
 
-static AdjointWork adjoint_work(const lbm_ctx* c, const Tiling& t) {
-  auto up = [](size_t b) { return ((b + 255) / 256) * 256; };
-  AdjointWork w;
-  w.dbar_off = up(static_cast<size_t>(c->g.n) * 11 * sizeof(float));
-  const size_t dbar = c->ph.regularized ? static_cast<size_t>(c->g.nz) * c->g.zstride * sizeof(float) : 0;
-  w.parts_off = w.dbar_off + up(dbar);
-  w.bytes = w.parts_off + static_cast<size_t>(t.blocks > 0 ? t.blocks : 0) * 3 * sizeof(double);
-  return w;
+lbm_status lbm_set_adjoint_tiling(lbm_ctx* c, int32_t shape, int32_t zchunk) {
+  if (!c || shape < -1 || shape >= ADJOINT_SHAPES || zchunk < 0) return LBM_EINVAL;
+  c->adj_shape = shape;
+  c->adj_zchunk = zchunk;
+  return LBM_OK;
+}
+
+// Workspace of one reverse step: the FP64 partial sums (dL/dG, dL/dtau_A,
+// dL/dtau_B) of each workgroup of the reverse march.
+static size_t adjoint_work(const Tiling& t) {
+  return static_cast<size_t>(t.blocks > 0 ? t.blocks : 0) * 3 * sizeof(double);
 }
 
 size_t lbm_adjoint_work_bytes(const lbm_ctx* c) {
   if (!c) return 0;
-  return adjoint_work(c, adjoint_tiling(c)).bytes;
+  return adjoint_work(adjoint_tiling(c));
 }
 
 lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, float* lam_out, void* work,
@@ -377,38 +396,18 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, fl
   if (work_bytes < lbm_adjoint_work_bytes(c)) return LBM_EINVAL;
   if (lam_in == lam_out || static_cast<const void*>(lam_in) == x_t || static_cast<const void*>(lam_out) == x_t)
     return LBM_EINVAL;
-  if (c->storage != Storage::F32) return LBM_ENOTSUP;
+  if (c->storage != Storage::F32 || c->ph.regularized == 2) return LBM_ENOTSUP;
   const Tiling t = adjoint_tiling(c);
   if (t.blocks <= 0) return LBM_ENOTSUP;
-  const AdjointWork w = adjoint_work(c, t);
-  char* base = static_cast<char*>(work);
-  float* m = reinterpret_cast<float*>(base);
-  float* sbar = m + 5 * c->g.n;
-  float* dbar = c->ph.regularized ? reinterpret_cast<float*>(base + w.dbar_off) : nullptr;
-  double* parts = reinterpret_cast<double*>(base + w.parts_off);
-  MarchIO io;
-  io.src = x_t;
+  AdjointIO io;
+  io.x_t = x_t;
   io.links = c->links;
-  io.lam = lam_in;
-  io.m = m;
-  io.sbar = sbar;
-  io.dbar = dbar;
-  io.partials = parts;
-  hipError_t e = launch_march(Storage::F32, Mode::Adjoint, c->g, c->ph, t, io, c->stream);
-  if (e == hipSuccess) e = launch_finalize(parts, t.blocks, 3, -1, dparams, true, c->stream);
-  if (e == hipSuccess) e = launch_adjoint_gather(c->g, c->links, m, sbar, c->stream);
-  if (e == hipSuccess) {
-    if (dbar) {
-      // The regularized march stored the direct term c_k c_k : Pbar of each
-      // pair in dbar: the stream pass pulls it in place of lam with weight 1
-      // (omega = 0 gives 1 - omega = 1).
-      Phys unit = c->ph;
-      unit.omega[0] = unit.omega[1] = 0.0f;
-      e = launch_adjoint_stream(c->g, unit, c->links, dbar, m, lam_out, drho0, true, c->stream);
-    } else {
-      e = launch_adjoint_stream(c->g, c->ph, c->links, lam_in, m, lam_out, drho0, false, c->stream);
-    }
-  }
+  io.lam_in = lam_in;
+  io.lam_out = lam_out;
+  io.partials = static_cast<double*>(work);
+  io.drho0 = drho0;
+  hipError_t e = launch_adjoint_march(c->g, c->ph, t, io, c->stream);
+  if (e == hipSuccess) e = launch_finalize(io.partials, t.blocks, 3, -1, dparams, true, c->stream);
   return from_hip(e);
 }
 

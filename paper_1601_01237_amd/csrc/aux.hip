@@ -47,6 +47,14 @@ __device__ __forceinline__ uint64_t pm_at(int s, int i, const Coord& p, int dx, 
          row_pos<T>(static_cast<int>(x), g);
 }
 
+// State-layout index of the residual row of species s's rest population at
+// cell p (16-bit forms, launch.h).
+template <typename T>
+__device__ __forceinline__ uint64_t res_at(int s, const Coord& p, const Grid& g) {
+  return static_cast<uint64_t>(p.z) * g.zstride + row_off(p.y, g) + static_cast<uint64_t>(RES_ROW + s) * g.pstride +
+         row_pos<T>(p.x, g);
+}
+
 // Canonical SoA index (s * 19 + i) * N + c of the FP32 population interface.
 __device__ __forceinline__ uint64_t soa(int s, int i, uint64_t c, const Grid& g) {
   return static_cast<uint64_t>(s * Q + i) * g.n + c;
@@ -87,7 +95,12 @@ __global__ void init_kernel(const Grid g, const Phys ph, const uint32_t* __restr
           v = static_cast<float>(weight_d(i) * rho0[s * g.n + src]);
         }
         if constexpr (Tr::shifted) v -= wshift(ph, s, i);
-        dst[pm_at<typename Tr::T>(s, i, p, 0, 0, 0, g)] = Tr::encode(v);
+        const auto q = Tr::encode(v);
+        dst[pm_at<typename Tr::T>(s, i, p, 0, 0, 0, g)] = q;
+        // the rest population keeps its rounding error in the residual row
+        if constexpr (Tr::shifted) {
+          if (i == 0) dst[res_at<typename Tr::T>(s, p, g)] = Tr::encode((v - Tr::decode(q)) * Tr::res_scale);
+        }
       }
     }
   }
@@ -111,7 +124,10 @@ __global__ void get_pop_kernel(const Grid g, const Phys ph, const uint32_t* __re
           const bool bb = (i != 0) && ((lk >> i) & 1u);
           const uint64_t at = bb ? pm_at<typename Tr::T>(s, opp(i), p, 0, 0, 0, g) : pm_at<typename Tr::T>(s, i, p, -CX[i], -CY[i], -CZ[i], g);
           v = Tr::decode(src[at]);
-          if constexpr (Tr::shifted) v += wshift(ph, s, i);
+          if constexpr (Tr::shifted) {
+            if (i == 0) v += Tr::decode(src[res_at<typename Tr::T>(s, p, g)]) * (1.0f / Tr::res_scale);
+            v += wshift(ph, s, i);
+          }
         }
         f[soa(s, i, c, g)] = v;
       }
@@ -140,7 +156,11 @@ __global__ void set_pop_kernel(const Grid g, const Phys ph, const uint32_t* __re
           v = f[soa(s, pop, at, g)];
         }
         if constexpr (Tr::shifted) v -= wshift(ph, s, j);
-        dst[pm_at<typename Tr::T>(s, j, p, 0, 0, 0, g)] = Tr::encode(v);
+        const auto q = Tr::encode(v);
+        dst[pm_at<typename Tr::T>(s, j, p, 0, 0, 0, g)] = q;
+        if constexpr (Tr::shifted) {
+          if (j == 0) dst[res_at<typename Tr::T>(s, p, g)] = Tr::encode((v - Tr::decode(q)) * Tr::res_scale);
+        }
       }
     }
   }
@@ -185,17 +205,15 @@ __global__ void __launch_bounds__(256) stream_copy_kernel(const u32x4* __restric
 // 128 x 4 column tile marches its chunk of z planes (the step's automatic
 // tiling for FP32), and per plane every lane loads the 38 population values
 // of its cell, then stores them (non-temporal) at the same place in dst.  No
-// halo and no re-read: it moves exactly the step's algorithmic bytes, so its
-// rate is the ceiling of that access pattern on the device.
+// halo and no re-read: it moves exactly the step's algorithmic bytes (with
+// the residual rows of the 16-bit forms), so its rate is the ceiling of that
+// access pattern on the device.
 template <typename T>
 __global__ void __launch_bounds__(512) march_copy_kernel(const Grid g, const Tiling tl, const T* __restrict__ src,
                                                          T* __restrict__ dst) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int tiles_xy = tl.tiles_x * tl.tiles_y;
-  const int bz = b / tiles_xy;
-  const int rem = b - bz * tiles_xy;
-  const int byy = rem / tl.tiles_x;
-  const int bxx = rem - byy * tl.tiles_x;
+  const TileCoord tc = tile_of_block(b, tl);
+  const int bxx = tc.x, byy = tc.y, bz = tc.z;
   const int x = bxx * 128 + static_cast<int>(threadIdx.x & 127u);
   const int y = byy * 4 + static_cast<int>(threadIdx.x >> 7);
   if (x >= g.nx || y >= g.ny) return;  // no barriers below
@@ -203,11 +221,12 @@ __global__ void __launch_bounds__(512) march_copy_kernel(const Grid g, const Til
   const int z1 = min((bz + 1) * tl.zchunk, g.nz);
   for (int z = bz * tl.zchunk; z < z1; ++z) {
     const uint64_t base = static_cast<uint64_t>(z) * g.zstride + col;
-    T v[2 * Q];
+    constexpr int R = block_rows(sizeof(T));
+    T v[R];
 #pragma unroll
-    for (int i = 0; i < 2 * Q; ++i) v[i] = src[base + static_cast<uint64_t>(i) * g.pstride];
+    for (int i = 0; i < R; ++i) v[i] = src[base + static_cast<uint64_t>(i) * g.pstride];
 #pragma unroll
-    for (int i = 0; i < 2 * Q; ++i) __builtin_nontemporal_store(v[i], &dst[base + static_cast<uint64_t>(i) * g.pstride]);
+    for (int i = 0; i < R; ++i) __builtin_nontemporal_store(v[i], &dst[base + static_cast<uint64_t>(i) * g.pstride]);
   }
 }
 
@@ -228,7 +247,7 @@ Layout state_layout(int nx, int ny, int elem_bytes) {
   if (padded % 65536 == 0) padded += 256;
   L.pstride = static_cast<uint32_t>(padded / elem_bytes);
   const uint64_t blocks = (static_cast<uint64_t>(ny) + L.brows - 1) / L.brows;
-  L.zstride = static_cast<uint64_t>(2 * Q) * L.pstride * blocks;
+  L.zstride = static_cast<uint64_t>(block_rows(elem_bytes)) * L.pstride * blocks;
   return L;
 }
 

@@ -20,12 +20,24 @@ __device__ __forceinline__ float density(float d, float shift) {
   }
 }
 
+// Row of a row block that holds direction i of species s; i = Q stands for
+// the residual of the rest population (16-bit forms only, launch.h).
+__host__ __device__ constexpr int store_row(int s, int i) { return i < Q ? s * Q + i : RES_ROW + s; }
+
 // Store of one species' post-collision populations f* in the 16-bit forms:
 // the 18 moving populations are rounded as f*_i - w_i rho_shift, and the rest
-// population takes the stored remainder D - sum_{i>0} decode(q_i), so that the
-// stored values of the cell still sum to D (up to the rounding of that one
-// value) and the density is not drifted by the rounding of the others.
-// `put(i, q)` receives the stored value of direction i.
+// population takes the stored remainder e = D - sum_{i>0} decode(q_i), so
+// that the stored values of the cell still sum to D and the density is not
+// drifted by the rounding of the others.  The remainder is kept in two 16-bit
+// values, q_0 = round(e) and the residual round((e - decode(q_0)) s) with s =
+// res_scale, which read back as decode(q_0) + decode(residual) / s: the
+// rounding left in the stored sum (and in the mass) is
+// then that of the residual, 2^-11 (FP16) or 2^-8 (BF16) times that of a
+// single value.  A single rounding of the rest population drifted the mass
+// by 1e-2 (FP16) over 2000 steps of a droplet that persists, where the field
+// keeps changing slowly and the roundings of successive steps are
+// correlated.  `put(i, q)` receives the stored value of direction i, with
+// i = Q for the residual.
 template <Storage S, typename Put>
 __device__ __forceinline__ void encode_species(const float f[Q], float d, const float ws[3], Put put) {
   using Tr = StorageTraits<S>;
@@ -37,7 +49,10 @@ __device__ __forceinline__ void encode_species(const float f[Q], float d, const 
     dsum = i == 1 ? back : dsum + back;
     put(i, q);
   }
-  put(0, Tr::encode(d - dsum));
+  const float e = d - dsum;
+  const auto q0 = Tr::encode(e);
+  put(0, q0);
+  put(Q, Tr::encode((e - Tr::decode(q0)) * Tr::res_scale));
 }
 
 // ---------------------------------------------------------------------------
@@ -207,12 +222,18 @@ __device__ __forceinline__ void collide(float f[2][Q], const Local& L, const Phy
 }
 
 // Regularized collision, Eqs. (10)-(11): f* = E(rho^a, u + g^a) +
-// (1 - w) w_i (c_i c_i - T0 I) : Pi^a / (2 T0^2), the second-order Hermite
-// projection of the non-equilibrium part, with
-// Pi^a = sum_i c_i c_i f_i - rho^a (T0 I + u u) (the second moment of Eq. 3
-// is exactly rho (T0 I + u u) on D3Q19).  The projection is even in c_i, so
-// both members of a pair get the same non-equilibrium part.  The rest
-// population is again the remainder rho^a - sum_{i>0} f*_i.
+// (1 - w) f^neq with f^neq the Hermite projection of the non-equilibrium part
+// f - E(rho^a, u):
+//   momentum flux   w_i (c_i c_i - T0 I) : Pi^a / (2 T0^2), with
+//                   Pi^a = sum_i c_i c_i f_i - rho^a (T0 I + u u) (the second
+//                   moment of Eq. 3 is exactly rho (T0 I + u u) on D3Q19);
+//                   even in c_i, so both members of a pair get it;
+//   energy flux     (ENERGY only) w_i H_i . q / (2 T0^3) with the contracted
+//                   third-order polynomials H_{i,a} = sum_{b != a} (c_a c_b^2
+//                   - T0 c_a) and q_a = sum_i H_{i,a} (f_i - E_i(rho^a, u));
+//                   odd in c_i.  2 T0^3 is the polynomials' norm on D3Q19.
+// The rest population is again the remainder rho^a - sum_{i>0} f*_i.
+template <bool ENERGY = false>
 __device__ __forceinline__ void collide_regularized(float f[2][Q], const Local& L, const Phys& ph) {
   const float ux = L.u[0], uy = L.u[1], uz = L.u[2];
 #pragma unroll
@@ -239,6 +260,37 @@ __device__ __forceinline__ void collide_regularized(float f[2][Q], const Local& 
     h[6] = fmaf(-2.0f, pxz, pxx + pzz) - tt;
     h[7] = fmaf(2.0f, pyz, pyy + pzz) - tt;
     h[8] = fmaf(-2.0f, pyz, pyy + pzz) - tt;
+    // Energy flux: odd part o_k = w_k H_k . q / (2 T0^3) of pair k, from the
+    // pair differences of f - E(rho^a, u) (E's odd part is
+    // 2 w rho cu (3 + 4.5 cu^2 - 4.5 uu)).  On D3Q19, H_k is -2/3 along the
+    // axis of a face pair and 1/3 per non-zero component of an edge pair.
+    float o[9];
+    if constexpr (ENERGY) {
+      const float uu = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+      const float bu = fmaf(-4.5f, uu, 3.0f);
+      float d[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const float cu = pair_dot(k, ux, uy, uz);
+        const float eo = (2.0f * pair_w(k) * r) * (cu * fmaf(4.5f, cu * cu, bu));
+        d[k] = (f[s][2 * k + 1] - f[s][2 * k + 2]) - eo;
+      }
+      const float third = 1.0f / 3.0f;
+      const float qx = fmaf(-2.0f * third, d[0], third * ((d[3] + d[4]) + (d[5] + d[6])));
+      const float qy = fmaf(-2.0f * third, d[1], third * ((d[3] - d[4]) + (d[7] + d[8])));
+      const float qz = fmaf(-2.0f * third, d[2], third * ((d[5] - d[6]) + (d[7] - d[8])));
+      const float keep = 1.0f - ph.omega[s];
+      // 13.5 w_k (H_k . q): -0.5 q_a for the face pairs, 0.125 (q_a +- q_b) for the edges
+      o[0] = keep * (-0.5f * qx);
+      o[1] = keep * (-0.5f * qy);
+      o[2] = keep * (-0.5f * qz);
+      o[3] = keep * (0.125f * (qx + qy));
+      o[4] = keep * (0.125f * (qx - qy));
+      o[5] = keep * (0.125f * (qx + qz));
+      o[6] = keep * (0.125f * (qx - qz));
+      o[7] = keep * (0.125f * (qy + qz));
+      o[8] = keep * (0.125f * (qy - qz));
+    }
     const float vx = ux + L.g[s][0], vy = uy + L.g[s][1], vz = uz + L.g[s][2];
     const float vv = fmaf(vx, vx, fmaf(vy, vy, vz * vz));
     const float av = fmaf(-1.5f, vv, 1.0f);
@@ -253,8 +305,13 @@ __device__ __forceinline__ void collide_regularized(float f[2][Q], const Local& 
       const float ov = cv * fmaf(4.5f, tv, bv);
       const float w = pair_w(k);
       const float neq = w * (keep45 * h[k]);
-      f[s][2 * k + 1] = fmaf(w * r, ev + ov, neq);
-      f[s][2 * k + 2] = fmaf(w * r, ev - ov, neq);
+      if constexpr (ENERGY) {
+        f[s][2 * k + 1] = fmaf(w * r, ev + ov, neq + o[k]);
+        f[s][2 * k + 2] = fmaf(w * r, ev - ov, neq - o[k]);
+      } else {
+        f[s][2 * k + 1] = fmaf(w * r, ev + ov, neq);
+        f[s][2 * k + 2] = fmaf(w * r, ev - ov, neq);
+      }
       moving += f[s][2 * k + 1] + f[s][2 * k + 2];
     }
     f[s][0] = r - moving;

@@ -49,9 +49,13 @@ template <> struct StorageTraits<Storage::F32> {
 // and subtract w_shift).  (Mixed-precision FMAs would fuse a conversion and
 // the shift into one instruction, but measured slower on gfx950 than convert
 // plus add.)
+// res_scale: the residual of a rest population (launch.h) is stored
+// multiplied by this power of two, which keeps it clear of the FP16
+// subnormals (the residual is at most 2^-11 of the value it corrects).
 template <> struct StorageTraits<Storage::F16> {
   using T = _Float16;
   static constexpr bool shifted = true;
+  static constexpr float res_scale = 2048.0f;
   __device__ static inline float decode(_Float16 v) { return static_cast<float>(v); }
   __device__ static inline _Float16 encode(float v) { return static_cast<_Float16>(v); }
   // Halves of a 32-bit word of a folded row, and the bits of one value.
@@ -69,6 +73,7 @@ template <> struct StorageTraits<Storage::F16> {
 template <> struct StorageTraits<Storage::BF16> {
   using T = uint16_t;
   static constexpr bool shifted = true;
+  static constexpr float res_scale = 1.0f;
   __device__ static inline float decode(uint16_t v) {
     return __uint_as_float(static_cast<uint32_t>(v) << 16);
   }

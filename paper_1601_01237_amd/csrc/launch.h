@@ -11,9 +11,11 @@ namespace lbm {
 // Per-launch description of the grid and the physics, shared by every kernel.
 // The stored state of one z plane is a sequence of row blocks of `brows` y
 // rows each; a row block holds, population after population, the rows of
-// all 38 populations (pstride elements apart).  Element (a, i, x, y, z) sits
-// at z * zstride + (y / brows) * 38 * pstride + (a * 19 + i) * pstride +
-// (y % brows) * nx + pos(x).
+// all 38 populations (pstride elements apart), and in the 16-bit forms two
+// residual rows (Layout).  Element (a, i, x, y, z) sits at z * zstride +
+// (y / brows) * 38 * pstride + (a * 19 + i) * pstride + (y % brows) * nx +
+// pos(x); FP32 blocks hold 38 rows, while the 16-bit forms have one block per
+// plane (brows = ny), so the block stride never applies to them.
 struct Grid {
   int nx, ny, nz;
   uint32_t nxy;      // nx * ny
@@ -38,6 +40,14 @@ struct Layout {
   uint32_t pstride;
   uint64_t zstride;
 };
+
+// Rows of one row block: the 38 population rows, and for the 16-bit forms
+// two more (row 38 + a): the residual of species a's rest population, the
+// rounding error of its stored value, itself stored in the same 16-bit form
+// (see encode_species).  Row r of a block starts r * pstride elements in.
+constexpr int POP_ROWS = 2 * Q;
+constexpr int RES_ROW = 2 * Q;
+__host__ __device__ constexpr int block_rows(int elem_bytes) { return elem_bytes == 4 ? POP_ROWS : POP_ROWS + 2; }
 Layout state_layout(int nx, int ny, int elem_bytes);
 
 struct Phys {
@@ -45,23 +55,45 @@ struct Phys {
   float g_ab, g_ba;   // G^{AB}, G^{BA}
   float rho_wall[2];  // rho_s^a
   float shift[2];     // rho_shift^a of the 16-bit storage forms (0 for FP32)
-  int regularized;    // collision operator: 0 = BGK (Eq. 2), 1 = regularized (Eqs. 10-11)
+  int regularized;    // collision operator: 0 = BGK (Eq. 2); regularized (Eqs. 10-11) with the
+                      // momentum flux (1) or the momentum and energy flux (2)
 };
+
+// Order of the workgroups over the (z chunk, tile) pairs.  The hardware
+// hands consecutive workgroups to the 8 XCDs in turn; xcd_remap makes each
+// XCD's share a contiguous range b0..b1 of the order, so the order decides
+// which tiles share an XCD's L2 while they run: with PLANE orders an XCD
+// takes whole rows (X: x fastest) or columns (Y: y fastest) of tiles of one
+// z chunk, with TILE orders every chunk of a run of tiles.
+enum BlockOrder : int { ORDER_PLANE_X = 1, ORDER_PLANE_Y = 2, ORDER_TILE_X = 3, ORDER_TILE_Y = 4 };
+constexpr int BLOCK_ORDERS = 4;
 
 struct Tiling {
   int tile;      // workgroup tile shape (index into the shapes of march.hip)
   int zchunk;    // z planes marched per workgroup
   int tiles_x, tiles_y, tiles_z;
   int blocks;
+  int order;     // BlockOrder
 };
+
+struct TileCoord {
+  int x, y, z;  // tile column, tile row, z chunk
+};
+
+__host__ __device__ inline TileCoord tile_of_block(int b, const Tiling& t) {
+  const int txy = t.tiles_x * t.tiles_y;
+  const bool chunk_fastest = t.order == ORDER_TILE_X || t.order == ORDER_TILE_Y;
+  const int z = chunk_fastest ? b % t.tiles_z : b / txy;
+  const int rem = chunk_fastest ? b / t.tiles_z : b - z * txy;
+  if (t.order == ORDER_PLANE_Y || t.order == ORDER_TILE_Y) return {rem / t.tiles_y, rem % t.tiles_y, z};
+  return {rem % t.tiles_x, rem / t.tiles_x, z};
+}
 
 // Tile shapes: 0 = 64x8, 1 = 64x12, 2 = 32x16, 3 = 128x4, 4 = 64x4, 5 = 256x2 cells
 // (one cell per lane); 6 = 64x8, 7 = 32x16, 8 = 32x8, 9 = 32x12 words of a
 // folded 16-bit row (two cells per lane; 16-bit storage, even nx, no walls).
 constexpr int TILE_SHAPES = 10;
 constexpr bool pair_shape(int tile) { return tile >= 6 && tile < TILE_SHAPES; }
-// Shapes the adjoint march is built for.
-constexpr bool adjoint_shape(int tile) { return tile == 0 || tile == 2 || tile == 4; }
 // zchunk <= 0 picks a default; open_box (a step without walls) takes the
 // round-count rule of march.hip.
 Tiling make_tiling(const Grid& g, int tile, int zchunk, bool open_box = false);
@@ -75,7 +107,7 @@ struct Region {
   float p_g;  // symmetric coupling used in the pressure
 };
 
-enum class Mode : int { Step = 0, Moments = 1, Adjoint = 2 };
+enum class Mode : int { Step = 0, Moments = 1 };
 
 struct MarchIO {
   const void* src = nullptr;       // stored state X_t
@@ -83,13 +115,28 @@ struct MarchIO {
   const uint32_t* links = nullptr; // wall link bits or null
   float* rho_out = nullptr;        // Moments
   float* uf_out = nullptr;         // Moments
-  double* partials = nullptr;      // Moments (16 per block) / Adjoint (3 per block)
+  double* partials = nullptr;      // Moments: 16 per block
   Region region{};
-  const float* lam = nullptr;      // Adjoint: lam_{t+1}
-  float* m = nullptr;              // Adjoint: 5 N  (a^A, a^B, b_x, b_y, b_z)
-  float* sbar = nullptr;           // Adjoint: 6 N  (Sbar^A xyz, Sbar^B xyz)
-  float* dbar = nullptr;           // Adjoint, regularized: per-pair direct term of dL/df (state layout)
 };
+
+// One reverse step (adjoint_march.hip): lam_t = dL/dX_t from lam_{t+1} =
+// dL/dX_{t+1} at the stored FP32 state X_t.
+struct AdjointIO {
+  const void* x_t = nullptr;        // stored state X_t (FP32, state layout)
+  const uint32_t* links = nullptr;  // wall link bits or null
+  const float* lam_in = nullptr;    // lam_{t+1} (state layout)
+  float* lam_out = nullptr;         // lam_t (state layout)
+  double* partials = nullptr;       // 3 per block: dL/dG (tied), dL/dtau_A, dL/dtau_B
+  double* drho0 = nullptr;          // 2 N, sum_i w_i dL/df_i^a, or null
+};
+
+// Tile shapes of the reverse march: 0 = 64x8, 1 = 32x16, 2 = 32x8, 3 = 64x4
+// cells.  zchunk <= 0 picks the default chunk.
+constexpr int ADJOINT_SHAPES = 4;
+Tiling adjoint_march_tiling(const Grid& g, int shape, int zchunk);
+int adjoint_auto_shape(const Grid& g, bool walls, int collision);
+hipError_t launch_adjoint_march(const Grid& g, const Phys& ph, const Tiling& t, const AdjointIO& io,
+                                hipStream_t st);
 
 hipError_t launch_march(Storage s, Mode mode, const Grid& g, const Phys& ph, const Tiling& t,
                         const MarchIO& io, hipStream_t st);
@@ -108,13 +155,6 @@ hipError_t launch_set_populations(Storage s, const Grid& g, const Phys& ph, cons
 // max_index (-1: none) takes the maximum instead of the sum.
 hipError_t launch_finalize(const double* partials, int blocks, int nvals, int max_index, double* out,
                            bool accumulate, hipStream_t st);
-hipError_t launch_adjoint_gather(const Grid& g, const uint32_t* links, float* m, const float* sbar,
-                                 hipStream_t st);
-// pairs: lam_in holds the regularized collision's per-pair direct term (see
-// adjoint.hip) instead of lam_{t+1}.
-hipError_t launch_adjoint_stream(const Grid& g, const Phys& ph, const uint32_t* links,
-                                 const float* lam_in, const float* m, float* lam_out,
-                                 double* drho0, bool pairs, hipStream_t st);
 hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStream_t st);
 hipError_t launch_march_copy(Storage s, const Grid& g, const void* src, void* dst, hipStream_t st);
 hipError_t launch_adjoint_seed(const Grid& g, const uint32_t* links, const float* grad_rho,

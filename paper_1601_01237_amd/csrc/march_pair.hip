@@ -60,20 +60,26 @@ __device__ __forceinline__ PairColumn make_pair_column(int d, int ey, const Grid
 
 __device__ __forceinline__ uint32_t trade_halves(uint32_t w) { return __builtin_amdgcn_alignbit(w, w, 16); }
 
-// Pull (Eq. 1) of the 19 words of species s for the two cells of column c:
-// the loads, then (fold_fix, once the words are in) the trade of halves for
-// the sources across the fold.
+// Words of one species per column: the 19 directions, then (index Q) the
+// residual of the rest population (launch.h).
+constexpr int QW = Q + 1;
+
+// Pull (Eq. 1) of the words of species s for the two cells of column c: the
+// loads, then (fold_fix, once the words are in) the trade of halves for the
+// sources across the fold.  The rest population and its residual come from
+// the column itself.
 template <Storage S>
 __device__ __forceinline__ void pull_words(const __amdgpu_buffer_rsrc_t rz[3], uint32_t ppb, const PairColumn& c,
-                                           int s, uint32_t w[Q]) {
+                                           int s, uint32_t w[QW]) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const uint32_t off = c.y[1 - CY[i]] + c.x[1 - CX[i]];
     w[i] = __builtin_amdgcn_raw_buffer_load_b32(rz[1 - CZ[i]], off, static_cast<uint32_t>(s * Q + i) * ppb, 0);
   }
+  w[Q] = __builtin_amdgcn_raw_buffer_load_b32(rz[1], c.y[1] + c.x[1], static_cast<uint32_t>(RES_ROW + s) * ppb, 0);
 }
 
-__device__ __forceinline__ void fold_fix(const PairColumn& c, uint32_t w[2][Q]) {
+__device__ __forceinline__ void fold_fix(const PairColumn& c, uint32_t w[2][QW]) {
   if (c.swap_p) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -94,10 +100,10 @@ __device__ __forceinline__ void fold_fix(const PairColumn& c, uint32_t w[2][Q]) 
 
 // Stored sums D (direction order, as pull_species) of the low and high cell.
 template <Storage S>
-__device__ __forceinline__ void word_sums(const uint32_t w[Q], float& dl, float& dh) {
+__device__ __forceinline__ void word_sums(const uint32_t w[QW], float& dl, float& dh) {
   using Tr = StorageTraits<S>;
-  dl = Tr::lo(w[0]);
-  dh = Tr::hi(w[0]);
+  dl = Tr::lo(w[0]) + Tr::lo(w[Q]) * (1.0f / Tr::res_scale);
+  dh = Tr::hi(w[0]) + Tr::hi(w[Q]) * (1.0f / Tr::res_scale);
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     dl += Tr::lo(w[i]);
@@ -106,7 +112,7 @@ __device__ __forceinline__ void word_sums(const uint32_t w[Q], float& dl, float&
 }
 
 template <Storage S>
-__device__ __forceinline__ float4 ring_entry(const uint32_t w[2][Q], const Phys& ph, bool flip, float d[2][2]) {
+__device__ __forceinline__ float4 ring_entry(const uint32_t w[2][QW], const Phys& ph, bool flip, float d[2][2]) {
   word_sums<S>(w[0], d[0][0], d[1][0]);
   word_sums<S>(w[1], d[0][1], d[1][1]);
   const float4 r = make_float4(density<S>(d[0][0], ph.shift[0]), density<S>(d[0][1], ph.shift[1]),
@@ -117,13 +123,16 @@ __device__ __forceinline__ float4 ring_entry(const uint32_t w[2][Q], const Phys&
 // Populations f_i = X_i of cell c (0 = low, 1 = high half) of both species,
 // decoded exactly as the single-cell pull does.
 template <Storage S>
-__device__ __forceinline__ void decode_cell(const uint32_t w[2][Q], int c, const float ws[2][3], float f[2][Q]) {
+__device__ __forceinline__ void decode_cell(const uint32_t w[2][QW], int c, const float ws[2][3], float f[2][Q]) {
   using Tr = StorageTraits<S>;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-      f[s][i] = (c == 0 ? Tr::lo(w[s][i]) : Tr::hi(w[s][i])) + ws[s][i == 0 ? 0 : (i <= 6 ? 1 : 2)];
+    for (int i = 0; i < Q; ++i) {
+      float x = c == 0 ? Tr::lo(w[s][i]) : Tr::hi(w[s][i]);
+      if (i == 0) x += (c == 0 ? Tr::lo(w[s][Q]) : Tr::hi(w[s][Q])) * (1.0f / Tr::res_scale);
+      f[s][i] = x + ws[s][i == 0 ? 0 : (i <= 6 ? 1 : 2)];
+    }
   }
 }
 
@@ -153,7 +162,7 @@ __device__ __forceinline__ void pair_halo_pos(int h, int& hx, int& hy) {
 // the halo waves p_0 .. p_{k+1}; after it the own waves collide plane
 // p_{k-1} from slots (k-2), (k-1), k while the halo waves fill p_{k+2} into
 // slot (k+2) % 5, whose last readers finished before barrier k.
-template <Storage S, int BK, int ROWS, int HW, bool REG>
+template <Storage S, int BK, int ROWS, int HW, int REG>
 __global__ void __launch_bounds__(BK * ROWS + 64 * HW)
 march_pair_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
   using Sh = PairShape<BK, ROWS, HW>;
@@ -165,11 +174,8 @@ march_pair_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io
 
   const int tid = threadIdx.x;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int tiles_xy = tl.tiles_x * tl.tiles_y;
-  const int bz = b / tiles_xy;
-  const int rem = b - bz * tiles_xy;
-  const int byy = rem / tl.tiles_x;
-  const int bxx = rem - byy * tl.tiles_x;
+  const TileCoord tc = tile_of_block(b, tl);
+  const int bxx = tc.x, byy = tc.y, bz = tc.z;
   const int k0 = bxx * BK, y0 = byy * ROWS, z0 = bz * tl.zchunk;
   const int z1 = min(z0 + tl.zchunk, g.nz);
   const int kmax = z1 - z0 + 1;  // planes p_k = z0 - 1 + k for k = 0..kmax
@@ -196,10 +202,10 @@ march_pair_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io
     // nxt = p_k (its densities go into the ring before barrier k) and ahead =
     // p_{k+1}, loaded one iteration early so that its latency overlaps the
     // barrier and the collision of p_{k-1}.
-    uint32_t cur[2][Q], nxt[2][Q], ahead[2][Q];
+    uint32_t cur[2][QW], nxt[2][QW], ahead[2][QW];
     float cur_d[2][2] = {{0.f, 0.f}, {0.f, 0.f}}, nxt_d[2][2];  // stored sums [cell][species]
     int slot = 0;  // k % 5
-    auto load_plane = [&](int k, uint32_t w[2][Q]) {
+    auto load_plane = [&](int k, uint32_t w[2][QW]) {
       const int p = z0 - 1 + k;
       __amdgpu_buffer_rsrc_t rz[3];
       rz[0] = plane_rsrc<T>(io.src, wrap(p - 1, g.nz), g);
@@ -238,8 +244,8 @@ march_pair_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io
                                     {SC[2 * c + 1][0], SC[2 * c + 1][1], SC[2 * c + 1][2]}};
             Local L;
             make_local(ra, rb, u, Sc, ph, L);
-            if constexpr (REG) {
-              collide_regularized(f, L, ph);
+            if constexpr (REG != 0) {
+              collide_regularized<REG == 2>(f, L, ph);
             } else {
               collide(f, L, ph);
             }
@@ -254,9 +260,9 @@ march_pair_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
-              __builtin_amdgcn_raw_buffer_store_b32(cur[s][i], rd, col_b, static_cast<uint32_t>(s * Q + i) * ppb,
-                                                    STORE_NT);
+            for (int i = 0; i < QW; ++i)
+              __builtin_amdgcn_raw_buffer_store_b32(cur[s][i], rd, col_b,
+                                                    static_cast<uint32_t>(store_row(s, i)) * ppb, STORE_NT);
           }
         }
       }
@@ -264,7 +270,7 @@ march_pair_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
+        for (int i = 0; i < QW; ++i) {
           cur[s][i] = nxt[s][i];
           nxt[s][i] = ahead[s][i];
         }
@@ -299,7 +305,7 @@ march_pair_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io
 #pragma unroll
       for (int j = 0; j < Sh::HPL; ++j) {
         if (!has[j]) continue;
-        uint32_t w[2][Q];
+        uint32_t w[2][QW];
         float hd[2][2];
         pull_words<S>(rz, ppb, hcol[j], 0, w[0]);
         pull_words<S>(rz, ppb, hcol[j], 1, w[1]);
@@ -320,14 +326,14 @@ march_pair_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io
   }
 }
 
-template <Storage S, int BK, int ROWS, int HW, bool REG>
+template <Storage S, int BK, int ROWS, int HW, int REG>
 hipError_t launch_pair_shape(const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io, hipStream_t st) {
   using Sh = PairShape<BK, ROWS, HW>;
   hipLaunchKernelGGL((march_pair_kernel<S, BK, ROWS, HW, REG>), dim3(t.blocks), dim3(Sh::NT), 0, st, g, ph, t, io);
   return hipGetLastError();
 }
 
-template <Storage S, bool REG>
+template <Storage S, int REG>
 hipError_t launch_pair_reg(const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io, hipStream_t st) {
   switch (t.tile) {
     case 6: return launch_pair_shape<S, 64, 8, 3, REG>(g, ph, t, io, st);
@@ -340,7 +346,12 @@ hipError_t launch_pair_reg(const Grid& g, const Phys& ph, const Tiling& t, const
 
 template <Storage S>
 hipError_t launch_pair_storage(const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io, hipStream_t st) {
-  return ph.regularized ? launch_pair_reg<S, true>(g, ph, t, io, st) : launch_pair_reg<S, false>(g, ph, t, io, st);
+  switch (ph.regularized) {
+    case 0: return launch_pair_reg<S, 0>(g, ph, t, io, st);
+    case 1: return launch_pair_reg<S, 1>(g, ph, t, io, st);
+    case 2: return launch_pair_reg<S, 2>(g, ph, t, io, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace

@@ -8,7 +8,8 @@
   the droplet's centre of mass over a window of steps.
 * Spurious velocity of static droplets with unequal relaxation times inside
   and outside (Sec. 3), and contact angle / wall film against the
-  dimensionless wall potential alpha (Sec. 4.2.2).
+  dimensionless wall potential alpha (Sec. 4.2.2), for a sessile droplet and
+  for a slug between flat plates.
 
 Every time step runs in liblbm.so; this module only sets up inputs, calls the
 library and fits the reduced results on the host (:mod:`.fits`).
@@ -18,7 +19,7 @@ densities (the droplet dissolves), so the physical cases default to
 G = -2.6 (|G| rho ~ 2.7 > 2).  With BGK and the exact-difference force the
 step is unstable below tau ~ 0.8 at this coupling.
 
-    python -m paper_1601_01237_amd.experiments laplace|wall|incline|spurious|wetting [--n N]
+    python -m paper_1601_01237_amd.experiments laplace|wall|incline|spurious|wetting|slug [--n N]
         [--collision regularized]
 """
 
@@ -119,6 +120,57 @@ def wetting_sweep(alphas=(-0.3, -0.15, 0.0, 0.15, 0.3), rho0=1.0, G=G_PHYS, tau=
     return out
 
 
+# Scale of the wall potentials against the dimensionless wettability alpha
+# (Sec. 4.2.2): the paper multiplies alpha by its initial density of each
+# component, half of its total density; the same half of this build's total
+# density (1.0 + 0.03) is used here.
+RHO0_SLUG = 0.515
+
+
+def slug_between_plates(alpha, height=32, nx=128, ny=4, G=G_PHYS, tau=1.0, steps=10000, rho0=RHO0_SLUG,
+                        collision="bgk"):
+    """Static slug between flat plates (Sec. 4.2.2): species A fills the middle
+    half of a channel of the given fluid height (walls on z = 0 and
+    z = height + 1, x and y periodic, y thin so the case is two-dimensional).
+    Returns the contact angle through A from a circle fitted to each meniscus
+    in the x-z section (both walls, both menisci averaged), the film density
+    rho_A in the first fluid cell at the wall far from the slug, and the
+    equilibrium bulk densities."""
+    nz = height + 2
+    shape = (nz, ny, nx)
+    x0, x1 = nx // 4, 3 * nx // 4
+    rho_init, solid = inputs.slug_channel(shape, x0, x1, seed=5)
+    rho_wall = wall_potential(alpha, rho0)
+    sim = Sim(rho_init, tau=(tau, tau), G=G, solid=solid, rho_wall=rho_wall, collision=collision)
+    sim.step(steps)
+    rho, _, d = sim.moments()
+    rho_a = rho[0].cpu().numpy().mean(axis=1)  # (z, x): average over the thin y
+    sim.close()
+    zm = nz // 2
+    hi, lo = float(rho_a[zm, nx // 2]), float(rho_a[zm, 0])
+    level = 0.5 * (hi + lo)
+    rows = range(3, nz - 3)  # the rows next to the walls are left out of the fit
+    angles = []
+    for side, lo_x, hi_x in ((+1, 0, nx // 2), (-1, nx // 2, nx)):
+        # left meniscus: A on its right (side +1); right meniscus: A on its left
+        pts = fits.meniscus_points(rho_a, level, lo_x, hi_x, rows)
+        if len(pts) < 4:
+            angles.append(float("nan"))
+            continue
+        c, r = fits.circle_fit(pts)
+        xm = float(pts[:, 0].mean())
+        for zw in (0.5, nz - 1.5):
+            angles.append(fits.meniscus_angle(c, r, zw, side, xm))
+    return dict(alpha=alpha, rho_wall=list(rho_wall), theta=float(np.nanmean(angles)), thetas=angles,
+                film_rho_a=float(rho_a[1, 0]), rho_in=hi, rho_out=lo, nonfinite=d["nonfinite"],
+                max_uf=d["max_uf"], steps=steps, G=G, tau=tau)
+
+
+def slug_sweep(alphas=(-0.6, -0.4, -0.2, 0.0, 0.2, 0.4, 0.6), **kw):
+    """Contact angle and film density of the slug against alpha (Sec. 4.2.2)."""
+    return [slug_between_plates(a, **kw) for a in alphas]
+
+
 def droplet_com(rho_a, mask, thr):
     """Centre of mass (x, y, z) of cells with rho_A > thr inside ``mask`` (no wrap)."""
     sel = mask & (rho_a > thr)
@@ -157,11 +209,14 @@ def wall_droplet(shape=(40, 96, 96), radius=14.0, rho_wall=(0.0, 0.0), G=G_PHYS,
 
 
 def incline_drift(shape=(192, 192, 384), angle=30.0, radius=32.0, G=G_PHYS, tau=1.0, steps=10000,
-                  window=1000, thr=0.515, collision="bgk"):
-    """Droplet on the 30-degree plane of the inclined channel: drift over the last window."""
+                  window=1000, thr=0.515, collision="bgk", rho_wall=(0.0, 0.0)):
+    """Droplet on the 30-degree plane of the inclined channel (Sec. 4.2.3):
+    drift of the droplet's centre of mass over the last window, the largest
+    |u_F| at the end, and the static contact angle between a sphere fitted to
+    the droplet's interface and the plane."""
     nz, ny, nx = shape
     rho0, solid = inputs.inclined_channel(shape, angle_deg=angle, radius=radius, seed=0)
-    sim = Sim(rho0, tau=(tau, tau), G=G, solid=solid, collision=collision)
+    sim = Sim(rho0, tau=(tau, tau), G=G, solid=solid, rho_wall=rho_wall, collision=collision)
     tile, zchunk, _ = sim.tune(tiles=(-1, 1))  # the run itself is unchanged (restored bitwise)
     zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     zc = nz / 3.0
@@ -176,14 +231,27 @@ def incline_drift(shape=(192, 192, 384), angle=30.0, radius=32.0, G=G_PHYS, tau=
     c1, n1 = droplet_com(r1, region, thr)
     v, vec = fits.drift_velocity(c0, c1, window)
     fluid = int((~solid).sum())
+    # contact angle: interface cells of the droplet at least 3 cells off the plane
+    a = np.radians(angle)
+    normal = np.array([-np.sin(a), 0.0, np.cos(a)])
+    p0 = np.array([nx / 2.0, 0.0, zc])
+    hi = float(np.percentile(r1[region], 99.0))
+    lo = float(np.percentile(r1[~solid], 50.0))
+    pts = fits.interface_points(r1, region, 0.5 * (hi + lo), 0.2 * (hi - lo))
+    dist = (pts - p0) @ normal
+    pts = pts[dist > 3.0]
+    theta = float("nan")
+    if len(pts) >= 10:
+        center, rad = fits.sphere_fit(pts)
+        theta = fits.plane_contact_angle(center, rad, p0, normal)
     return dict(drift=v, drift_vec=vec.tolist(), cells=[n0, n1], droplet_volume_fraction=n1 / fluid,
-                nonfinite=d["nonfinite"], max_uf=d["max_uf"], G=G, tau=tau, steps=steps, window=window,
-                collision=collision, tile=tile, zchunk=zchunk)
+                theta=theta, nonfinite=d["nonfinite"], max_uf=d["max_uf"], G=G, tau=tau, steps=steps,
+                window=window, collision=collision, rho_wall=list(rho_wall), tile=tile, zchunk=zchunk)
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("case", choices=["laplace", "wall", "incline", "spurious", "wetting"])
+    ap.add_argument("case", choices=["laplace", "wall", "incline", "spurious", "wetting", "slug"])
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--G", type=float, default=G_PHYS)
@@ -199,6 +267,8 @@ def main():
         res = spurious_sweep(n=args.n, steps=args.steps or 4000, collision=args.collision)
     elif args.case == "wetting":
         res = wetting_sweep(G=args.G, steps=args.steps or 4000, collision=args.collision)
+    elif args.case == "slug":
+        res = slug_sweep(G=args.G, steps=args.steps or 10000, collision=args.collision)
     else:
         res = incline_drift(G=args.G, steps=args.steps or 10000, collision=args.collision)
     print(json.dumps(res, default=float))

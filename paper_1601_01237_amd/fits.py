@@ -10,7 +10,9 @@ measurements of arXiv 1601.01237:
   (Sec. 3, :func:`tanh_radius`) or from the volume of the droplet phase
   (:func:`equivalent_radius`);
 * static contact angle from a circle (here: sphere) fitted to the interface
-  (Sec. 4.2.2, :func:`sphere_fit`, :func:`contact_angle`);
+  (Sec. 4.2.2, :func:`sphere_fit`, :func:`contact_angle`); for a slug between
+  plates, a circle fitted to the meniscus in the x-z plane
+  (:func:`meniscus_points`, :func:`circle_fit`, :func:`meniscus_angle`);
 * droplet drift velocity from the change of the droplet's centre of mass
   between two times (Sec. 4.2.3, :func:`drift_velocity`).
 
@@ -112,9 +114,70 @@ def contact_angle(center, radius, wall_height):
     return math.degrees(math.acos(c))
 
 
+def plane_contact_angle(center, radius, point, normal):
+    """Angle inside a droplet between a wall plane (through ``point``, unit
+    ``normal`` pointing into the fluid) and the fitted sphere:
+    cos(theta) = -d / R with d the signed distance of the centre from the
+    plane, in degrees (the flat-wall form of :func:`contact_angle`)."""
+    n = np.asarray(normal, dtype=np.float64)
+    d = float(np.dot(np.asarray(center, dtype=np.float64) - np.asarray(point, dtype=np.float64), n))
+    return math.degrees(math.acos(max(-1.0, min(1.0, -d / radius))))
+
+
 def drift_velocity(com_a, com_b, steps, lengths=None):
     """|d(com)| / steps between two centres of mass (periodic minimum image if lengths given)."""
     d = np.asarray(com_b, dtype=np.float64) - np.asarray(com_a, dtype=np.float64)
     if lengths is not None:
         d = min_image(d, np.asarray(lengths, dtype=np.float64))
     return float(np.linalg.norm(d)) / steps, d / steps
+
+
+def circle_fit(points):
+    """Algebraic least-squares circle through points (N, 2): returns (centre, radius)."""
+    P = np.asarray(points, dtype=np.float64)
+    A = np.concatenate([2.0 * P, np.ones((P.shape[0], 1))], axis=1)
+    b = np.sum(P * P, axis=1)
+    sol, *_ = np.linalg.lstsq(A, b, rcond=None)
+    c = sol[:2]
+    return c, math.sqrt(sol[2] + float(c @ c))
+
+
+def meniscus_points(profile, level, x_lo, x_hi, rows):
+    """Interface of a slug seen in an x-z section.  ``profile`` is rho_A[z, x];
+    for each z in ``rows`` the position x in [x_lo, x_hi) where rho_A crosses
+    ``level`` (linear interpolation between the two cells that bracket it).
+    Returns an (N, 2) array of (x, z)."""
+    pts = []
+    for z in rows:
+        v = np.asarray(profile[z], dtype=np.float64)
+        for x in range(x_lo, x_hi - 1):
+            a, b = v[x] - level, v[x + 1] - level
+            if a == 0.0:
+                pts.append((float(x), float(z)))
+                break
+            if a * b < 0.0:
+                pts.append((x + a / (a - b), float(z)))
+                break
+    return np.array(pts, dtype=np.float64)
+
+
+def meniscus_angle(center, radius, z_wall, phase_a_side, x_ref):
+    """Contact angle, measured through phase A, between the wall z = z_wall and
+    a circular meniscus (centre (x_c, z_c), radius R) that crosses it.
+    ``phase_a_side`` is -1 when phase A lies at smaller x than the meniscus,
+    +1 when it lies at larger x; ``x_ref`` is a point of the meniscus (e.g.
+    the mean x of the fitted points), which picks the crossing on its side of
+    the centre.  With t the tangent of the circle at the contact point,
+    oriented away from the wall, cos(theta) = t . (phase_a_side, 0)."""
+    xc, zc = float(center[0]), float(center[1])
+    dz = z_wall - zc
+    if abs(dz) >= radius:
+        return float("nan")
+    side = 1.0 if x_ref >= xc else -1.0
+    rx, rz = side * math.sqrt(radius * radius - dz * dz), dz
+    away = 1.0 if dz < 0.0 else -1.0  # into the fluid, away from the wall
+    tx, tz = -rz, rx
+    if tz * away < 0.0:
+        tx, tz = -tx, -tz
+    c = (tx * phase_a_side) / radius
+    return math.degrees(math.acos(max(-1.0, min(1.0, c))))

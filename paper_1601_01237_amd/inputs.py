@@ -161,6 +161,22 @@ def flat_channel(shape, seed=0, noise=NOISE, radius=None):
     return rho0, solid
 
 
+def slug_channel(shape, x0, x1, seed=0, noise=NOISE):
+    """Walls on z = 0 and z = nz-1; species A fills the slab x0 <= x < x1 of
+    the fluid between them (a slug across the channel), species B the rest.
+    Returns ``(rho0, solid)``; ``rho0`` is zero on solid cells."""
+    nz, ny, nx = shape
+    solid = np.zeros(shape, dtype=bool)
+    solid[0] = True
+    solid[nz - 1] = True
+    rng = np.random.default_rng(seed)
+    x, _, _ = _grid(shape)
+    inside = (x >= x0) & (x < x1)
+    rho0 = _two_species(inside, rng, noise)
+    rho0[:, solid] = 0.0
+    return rho0, solid
+
+
 def target_ellipsoid(shape, radius, seed=0):
     """Target density of species A for the calibration objective.
 

@@ -44,9 +44,14 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SOURCES = ("march.hip", "march_pair.hip", "cell.h", "buffer.h", "lattice.h", "launch.h")
-BYTES_PER_CELL = {"fp32": 304, "fp16": 152, "bf16": 152}
-SHAPES = {"128": (128, 128, 128), "512": (512, 512, 512), "walls": (192, 192, 384)}
+# the step kernel, the reverse march and the launch choices (api.hip)
+KERNEL_SOURCES = ("march.hip", "march_pair.hip", "adjoint_march.hip", "adjoint_cell.h", "pull.h", "cell.h", "buffer.h",
+                  "lattice.h", "launch.h", "api.hip")
+BYTES_PER_CELL = {"fp32": 304, "fp16": 156, "bf16": 156}
+SHAPES = {"128": (128, 128, 128), "512": (512, 512, 512), "walls": (192, 192, 384), "adjoint96": (96, 96, 96)}
+# Algorithmic bytes per cell of one reverse step: X_t and lam_{t+1} read once,
+# lam_t written once (FP32).
+ADJOINT_BYTES_PER_CELL = 456
 
 
 def kernel_source_hash():
@@ -86,10 +91,11 @@ def copy_bytes(gib):
     return (int(gib * (1 << 30)) // 16) * 16
 
 
-def cmd_run(args):
+def _reference_copy(args):
+    """The calibration copy: ``--copy-reps`` launches of lbm_stream_copy over
+    ``--copy-gib`` GiB."""
     import torch
     from . import _lib
-    from .sim import Sim
     lib = _lib.load()
     n = copy_bytes(args.copy_gib)
     src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
@@ -102,10 +108,19 @@ def cmd_run(args):
     torch.cuda.synchronize()
     del src, dst
     print(f"[profiling] copied {args.copy_reps} x {n} bytes", flush=True)
+
+
+def cmd_run(args):
+    import torch
+    from . import _lib
+    from .sim import Sim
+    lib = _lib.load()
+    _reference_copy(args)
     shape, kw = workload(args.workload, args.storage, args.collision)
     sim = Sim(**kw)
     if args.zchunk or args.tile >= 0:
         sim.set_tiling(args.tile, args.zchunk)
+    sim.set_block_order(args.order)
     if args.march_copy:
         # the step's access pattern without arithmetic, on a copy of the state
         dst = torch.empty_like(sim.state)
@@ -126,9 +141,12 @@ def cmd_run_adjoint(args):
     from . import inputs
     from .autograd import Reverse
     from .sim import Sim
+    _reference_copy(args)
     n = args.n
     rho0 = inputs.sphere_droplet((n, n, n), radius=20.0 * n / 96.0, seed=0)
-    sim = Sim(rho0, tau=(1.0, 1.0), G=-1.0)
+    sim = Sim(rho0, tau=(1.0, 1.0), G=-1.0, collision=args.collision)
+    if args.shape >= 0 or args.zchunk:
+        sim.set_adjoint_tiling(args.shape, args.zchunk)
     sim.step(args.steps)
     rev = Reverse(sim)
     lam = rev.seed(torch.ones((2, n, n, n), dtype=torch.float32, device=sim.device))
@@ -161,20 +179,32 @@ def _is_step(name):
     return ("march_kernel" in name and "(lbm::Mode)0" in name) or "march_pair_kernel" in name
 
 
+def _is_adjoint(name):
+    return "adjoint_march_kernel" in name
+
+
 def cmd_traffic(args):
     known = copy_bytes(args.copy_gib)
     fetch, write = _rows(args.fetch, "FETCH_SIZE"), _rows(args.write, "WRITE_SIZE")
     c_rd, n_c = _mean_kib(fetch, _is_copy)
     c_wr, _ = _mean_kib(write, _is_copy)
-    s_rd, n_s = _mean_kib(fetch, _is_step)
-    s_wr, _ = _mean_kib(write, _is_step)
+    pick = _is_adjoint if args.workload.startswith("adjoint") else _is_step
+    s_rd, n_s = _mean_kib(fetch, pick)
+    s_wr, _ = _mean_kib(write, pick)
     f_rd = known / (c_rd * 1024.0)
     f_wr = known / (c_wr * 1024.0)
     rd = s_rd * 1024.0 * f_rd
     wr = s_wr * 1024.0 * f_wr
     shape = SHAPES[args.workload]
     cells = shape[0] * shape[1] * shape[2]
-    algo = BYTES_PER_CELL[args.storage] * cells
+    algo = (ADJOINT_BYTES_PER_CELL if args.workload.startswith("adjoint") else BYTES_PER_CELL[args.storage]) * cells
+    # With walls a step reads and writes the populations of fluid cells only:
+    # that is the algorithmic traffic; the all-cell figure is kept beside it.
+    fluid = cells
+    if args.workload == "walls":
+        _, kw = _workload("walls", args.storage)
+        fluid = int((~kw["solid"]).sum())
+    algo_fluid = BYTES_PER_CELL[args.storage] * fluid
     entry = {
         "kernel_hash": kernel_source_hash(),
         "bytes_per_launch": round(rd + wr),
@@ -182,6 +212,10 @@ def cmd_traffic(args):
         "write_bytes_per_launch": round(wr),
         "algorithmic_bytes_per_launch": algo,
         "traffic_over_algorithmic": round((rd + wr) / algo, 4),
+        "fluid_cells": fluid,
+        "algorithmic_bytes_fluid": algo_fluid,
+        "traffic_over_algorithmic_fluid": round((rd + wr) / algo_fluid, 4),
+        "read_over_algorithmic_fluid": round(rd / (algo_fluid / 2), 4),
         "fetch_scale": round(f_rd, 4),
         "write_scale": round(f_wr, 4),
         "step_dispatches": n_s,
@@ -197,21 +231,27 @@ def cmd_traffic(args):
     with open(args.json, "w") as f:
         json.dump(rec, f, indent=1, sort_keys=True)
         f.write("\n")
+    rfrac = 2.0 / 3.0 if pick is _is_adjoint else 0.5  # share of the algorithmic bytes that are reads
     lines = [
-        f"HBM traffic of the fused step, {args.workload_key} {args.storage} ({cells} cells)",
+        f"HBM traffic of the {'fused reverse step' if pick is _is_adjoint else 'fused step'}, "
+        f"{args.workload_key} {args.storage} ({cells} cells)",
         "",
         f"command: {args.command}",
         "",
         f"calibration (lbm_stream_copy, {known} bytes read and written per dispatch, {n_c} dispatches):",
         f"  FETCH_SIZE  {c_rd:14.1f} KiB/dispatch -> scale {f_rd:.4f}",
         f"  WRITE_SIZE  {c_wr:14.1f} KiB/dispatch -> scale {f_wr:.4f}",
-        f"step kernel ({n_s} dispatches):",
+        f"{'reverse-march' if pick is _is_adjoint else 'step'} kernel ({n_s} dispatches):",
         f"  FETCH_SIZE  {s_rd:14.1f} KiB/dispatch -> read  {rd / 1e6:10.2f} MB",
         f"  WRITE_SIZE  {s_wr:14.1f} KiB/dispatch -> write {wr / 1e6:10.2f} MB",
         f"  total {(rd + wr) / 1e6:.2f} MB per launch vs algorithmic {algo / 1e6:.2f} MB "
-        f"({(rd + wr) / algo:.3f}x); read {rd / (algo / 2):.3f}x, write {wr / (algo / 2):.3f}x",
+        f"({(rd + wr) / algo:.3f}x); read {rd / (algo * rfrac):.3f}x, write {wr / (algo * (1 - rfrac)):.3f}x",
         f"kernel source hash {entry['kernel_hash']}",
     ]
+    if fluid != cells:
+        lines.insert(-1, f"  fluid cells {fluid} ({fluid / cells:.3f} of all): algorithmic {algo_fluid / 1e6:.2f} MB; "
+                         f"total {(rd + wr) / algo_fluid:.3f}x, read {rd / (algo_fluid / 2):.3f}x, "
+                         f"write {wr / (algo_fluid / 2):.3f}x of it")
     with open(args.out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -220,6 +260,8 @@ def cmd_traffic(args):
 def _kernel_class(name):
     if _is_copy(name):
         return "lbm_stream_copy"
+    if _is_adjoint(name):
+        return "reverse"
     if "march_copy_kernel" in name:
         return "lbm_march_copy"
     if _is_step(name):
@@ -240,7 +282,7 @@ def cmd_counters(args):
                 key = (r["Counter_Name"], cls)
                 table.setdefault(key, []).append(float(r["Counter_Value"]))
     counters = sorted({k[0] for k in table})
-    classes = ["lbm_stream_copy", "lbm_march_copy", "step"]
+    classes = [c for c in ("lbm_stream_copy", "lbm_march_copy", "step", "reverse") if any(k[1] == c for k in table)]
     lines = [args.title, "", f"command: {args.command}", "",
              f"{'counter (mean per dispatch)':32} " + " ".join(f"{c:>18}" for c in classes)]
     for name in counters:
@@ -289,15 +331,21 @@ def main(argv=None):
     r.add_argument("--copy-reps", type=int, default=3)
     r.add_argument("--zchunk", type=int, default=0, help="z planes per workgroup (0 = the library's default)")
     r.add_argument("--tile", type=int, default=-1, help="tile shape (-1 = automatic)")
+    r.add_argument("--order", type=int, default=0, help="block order (0 = automatic, see lbm_set_block_order)")
     r.add_argument("--march-copy", type=int, default=0,
                    help="launches of lbm_march_copy (the step's access pattern) before the steps")
     ra = sub.add_parser("run-adjoint")
     ra.add_argument("--n", type=int, default=96)
     ra.add_argument("--steps", type=int, default=20)
+    ra.add_argument("--collision", default="bgk", choices=["bgk", "regularized"])
+    ra.add_argument("--shape", type=int, default=-1, help="reverse-march tile shape (-1 = automatic)")
+    ra.add_argument("--zchunk", type=int, default=0)
+    ra.add_argument("--copy-gib", type=float, default=2.0)
+    ra.add_argument("--copy-reps", type=int, default=3)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
-    t.add_argument("--workload", default="128", choices=["128", "512", "walls"])
+    t.add_argument("--workload", default="128", choices=["128", "512", "walls", "adjoint96"])
     t.add_argument("--workload-key", default="128^3")
     t.add_argument("--storage", default="fp32")
     t.add_argument("--copy-gib", type=float, default=2.0)

@@ -26,6 +26,13 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def layout_rows(storage):
+    """Rows of one row block of the state layout (lbm.h): the 38 population
+    rows, and for the 16-bit forms the residual rows of the two rest
+    populations."""
+    return 2 * Q + (0 if storage == "fp32" else 2)
+
+
 def coupling_matrix(G):
     """G as a 2x2 matrix; a scalar means G^{AB} = G^{BA} = G and G^{aa} = 0."""
     if np.isscalar(G):
@@ -45,11 +52,12 @@ class Sim:
     rho_shift : per-species shift of the 16-bit forms; default: mean density.
     solid : optional bool array (nz, ny, nx) of wall cells.
     rho_wall : wall potential rho_s^a (Sec. 4).
-    collision : "bgk" (Eq. 2) or "regularized" (Eqs. 10-11 of Sec. 3).
+    collision : "bgk" (Eq. 2), "regularized" (Eqs. 10-11 of Sec. 3, momentum
+        flux) or "regularized3" (the same filter keeping the energy flux).
     tile, zchunk : tiling of the step kernel (results do not depend on it).
     """
 
-    COLLISIONS = {"bgk": _lib.BGK, "regularized": _lib.REGULARIZED}
+    COLLISIONS = {"bgk": _lib.BGK, "regularized": _lib.REGULARIZED, "regularized3": _lib.REGULARIZED3}
 
     def __init__(self, rho0, tau=(1.0, 1.0), G=-1.0, storage="fp32", rho_shift=None,
                  solid=None, rho_wall=(0.0, 0.0), device="cuda:0", tile=None, zchunk=None,
@@ -88,12 +96,14 @@ class Sim:
         p.collision = self.COLLISIONS[collision]
         self.params = p
 
-        # Row-blocked state layout (lbm.h): (rows per block, population stride).
+        # Row-blocked state layout (lbm.h): (y rows per block, population
+        # stride, rows of population data per block: 38, plus the two residual
+        # rows of the rest populations in the 16-bit forms).
         self.pstride = int(self.lib.lbm_plane_stride(nx, ny, code))
-        self.layout = (int(self.lib.lbm_row_block(nx, ny, code)), self.pstride)
+        self.layout = (int(self.lib.lbm_row_block(nx, ny, code)), self.pstride, layout_rows(storage))
         self.state_elems = int(self.lib.lbm_state_elems(nx, ny, nz, code))
         self.lam_layout = (int(self.lib.lbm_row_block(nx, ny, _lib.FP32)),
-                           int(self.lib.lbm_plane_stride(nx, ny, _lib.FP32)))
+                           int(self.lib.lbm_plane_stride(nx, ny, _lib.FP32)), layout_rows("fp32"))
         self.lam_elems = int(self.lib.lbm_state_elems(nx, ny, nz, _lib.FP32))
         self.row_half = int(self.lib.lbm_row_half(nx, code, int(solid is not None)))
         # (the adjoint arrays are FP32 and only used with FP32 storage)
@@ -173,17 +183,31 @@ class Sim:
         _lib.check("lbm_set_tiling", self.lib.lbm_set_tiling(self.ctx, int(tile), int(zchunk)))
         self.tiling = (int(tile), int(zchunk))
 
-    def tune(self, zchunks=(0, 8, 12, 16, 24, 32, 48, 64), tiles=(-1,), steps=None):
-        """Time the step for every (tile shape, z chunk) pair of ``tiles`` x
-        ``zchunks`` (tile -1 = the library's automatic shape, zchunk 0 = its
-        default chunk; see lbm_set_tiling) and keep the fastest.  The state
-        and time level are restored afterwards (bitwise: every tiling computes
-        the same step), so tuning can precede any run.  Shapes the context
-        cannot run (pair shapes on unfolded rows, for instance) are skipped.
-        Returns (tile, zchunk, {(tile, zchunk): ms per step})."""
+    def set_block_order(self, order=0):
+        """Order of the step kernel's workgroups over (z chunk, tile) (0 = automatic, 1..4, see
+        lbm_set_block_order)."""
+        _lib.check("lbm_set_block_order", self.lib.lbm_set_block_order(self.ctx, int(order)))
+
+    def set_adjoint_tiling(self, shape=-1, zchunk=0):
+        """Tile shape of the reverse march (-1 = automatic, 0..3, see
+        lbm_set_adjoint_tiling) and z planes per workgroup (0 = default)."""
+        _lib.check("lbm_set_adjoint_tiling", self.lib.lbm_set_adjoint_tiling(self.ctx, int(shape), int(zchunk)))
+
+    def tune(self, zchunks=(0, 8, 12, 16, 24, 32, 48, 64), tiles=(-1,), steps=None, orders=(0,)):
+        """Time the step for every (tile shape, z chunk, block order) of
+        ``tiles`` x ``zchunks`` x ``orders`` (tile -1 = the library's automatic
+        shape, zchunk 0 = its default chunk, order 0 = its default order; see
+        lbm_set_tiling and lbm_set_block_order) and keep the fastest.  The
+        state and time level are restored afterwards (bitwise: every tiling
+        computes the same step), so tuning can precede any run.  Shapes the
+        context cannot run (pair shapes on unfolded rows, for instance) are
+        skipped.  Returns (tile, zchunk, {(tile, zchunk[, order]): ms per
+        step}); the keys carry the order only when more than one is tried,
+        and the chosen order stays set."""
         import torch
         nz = self.shape[0]
         cands = [z for z in dict.fromkeys(int(z) for z in zchunks) if z <= nz]
+        order_list = list(dict.fromkeys(int(o) for o in orders))
         n = int(steps) if steps else max(2, min(20, int(4e8 // self.n)))
         ckpt = self.checkpoint()
 
@@ -202,19 +226,23 @@ class Sim:
         while spent < 50.0:
             spent += timed(n)
         times = {}
-        for tile in dict.fromkeys(int(t) for t in tiles):
-            for z in cands:
-                try:
-                    self.set_tiling(tile, z)
-                except _lib.LBMError:
-                    break
-                self.step(1)
-                times[(tile, z)] = min(timed(n), timed(n)) / n  # best of two
+        for order in order_list:
+            self.set_block_order(order)
+            for tile in dict.fromkeys(int(t) for t in tiles):
+                for z in cands:
+                    try:
+                        self.set_tiling(tile, z)
+                    except _lib.LBMError:
+                        break
+                    self.step(1)
+                    key = (tile, z, order) if len(order_list) > 1 else (tile, z)
+                    times[key] = min(timed(n), timed(n)) / n  # best of two
         self.restore(ckpt)
         if not times:
             raise ValueError("no tiling of the candidates runs on this grid")
         best = min(times, key=times.get)
-        self.set_tiling(*best)
+        self.set_tiling(best[0], best[1])
+        self.set_block_order(best[2] if len(best) > 2 else order_list[0])
         return best[0], best[1], times
 
     @property
@@ -223,24 +251,37 @@ class Sim:
         return self.bufs[self.t & 1]
 
     def plane_view(self, flat, layout=None):
-        """(nz, nyb, 2, 19, B, nx) view of a flat state-layout buffer: z plane,
-        row block, species, population, row in the block, row position (see
-        :attr:`x_pos`).  Rows past ny in the last block are padding."""
+        """(nz, nyb, 2, 19, B, nx) view of the population rows of a flat
+        state-layout buffer: z plane, row block, species, population, row in
+        the block, row position (see :attr:`x_pos`).  Rows past ny in the last
+        block are padding."""
         nz, ny, nx = self.shape
-        b, ps = self.layout if layout is None else layout
+        b, ps, rows = self.layout if layout is None else layout
         nyb = -(-ny // b)
-        return flat.view(nz, nyb, 2, Q, ps)[..., : b * nx].unflatten(-1, (b, nx))
+        v = flat.view(nz, nyb, rows, ps)[:, :, : 2 * Q]
+        return v.unflatten(2, (2, Q))[..., : b * nx].unflatten(-1, (b, nx))
+
+    def residual_view(self, flat, layout=None):
+        """(nz, nyb, 2, B, nx) view of the residual rows of the rest
+        populations (16-bit forms; lbm.h): the stored rest population of
+        species a reads back as its value in the population row plus this."""
+        nz, ny, nx = self.shape
+        b, ps, rows = self.layout if layout is None else layout
+        if rows == 2 * Q:
+            raise ValueError("this layout has no residual rows")
+        nyb = -(-ny // b)
+        return flat.view(nz, nyb, rows, ps)[:, :, 2 * Q:][..., : b * nx].unflatten(-1, (b, nx))
 
     def live_mask(self, layout=None, dtype=None):
         """Boolean flat mask of the elements of a state-layout buffer that hold
-        a population value (not padding)."""
-        b, ps = self.layout if layout is None else layout
+        a population value or a residual (not padding)."""
+        b, ps, rows = self.layout if layout is None else layout
         nz, ny, nx = self.shape
-        n = nz * -(-ny // b) * 2 * Q * ps
-        m = torch.zeros(n, dtype=torch.bool, device=self.device)
-        v = self.plane_view(m, (b, ps))
-        for yb in range(v.shape[1]):
-            v[:, yb, :, :, : min(b, ny - yb * b)] = True
+        nyb = -(-ny // b)
+        m = torch.zeros(nz * nyb * rows * ps, dtype=torch.bool, device=self.device)
+        v = m.view(nz, nyb, rows, ps)[..., : b * nx].unflatten(-1, (b, nx))
+        for yb in range(nyb):
+            v[:, yb, :, : min(b, ny - yb * b)] = True
         return m
 
     def _row_order(self, flat):
@@ -249,17 +290,29 @@ class Sim:
 
     def cells(self, flat, z, y, x, layout=None):
         """Values (..., 2, 19) of a state-layout buffer at integer cell
-        coordinates z, y, x (tensors of one shape, on the buffer's device)."""
-        b, _ = self.layout if layout is None else layout
+        coordinates z, y, x (tensors of one shape, on the buffer's device).
+        In the 16-bit forms the rest population's residual is separate
+        (:meth:`cells_residual`)."""
+        b = (self.layout if layout is None else layout)[0]
         if self._row_order(flat):
             x = self.x_pos.to(flat.device)[x]
         v = self.plane_view(flat, layout)
         return v[z, torch.div(y, b, rounding_mode="floor"), :, :, y % b, x]
 
+    def cells_residual(self, flat, z, y, x, layout=None):
+        """Residuals (..., 2) of the rest populations at cells z, y, x (16-bit forms)."""
+        b = (self.layout if layout is None else layout)[0]
+        if self._row_order(flat):
+            x = self.x_pos.to(flat.device)[x]
+        v = self.residual_view(flat, layout)
+        return v[z, torch.div(y, b, rounding_mode="floor"), :, y % b, x]
+
     def to_state_layout(self, f, layout=None, elems=None):
-        """(2, 19, nz, ny, nx) array -> new flat state-layout buffer (zero padding)."""
+        """(2, 19, nz, ny, nx) array -> new flat state-layout buffer (zero padding
+        and, in the 16-bit forms, zero residual rows)."""
         nz, ny, nx = self.shape
-        b, ps = self.layout if layout is None else layout
+        lay = self.layout if layout is None else layout
+        b = lay[0]
         nyb = -(-ny // b)
         n = self.state_elems if elems is None else elems
         out = torch.zeros(n, dtype=f.dtype, device=f.device)
@@ -269,11 +322,12 @@ class Sim:
             rows[:, :, :, :ny, self.x_pos.to(f.device)] = src
         else:
             rows[:, :, :, :ny] = src
-        self.plane_view(out, (b, ps)).copy_(rows.view(2, Q, nz, nyb, b, nx).permute(2, 3, 0, 1, 4, 5))
+        self.plane_view(out, lay).copy_(rows.view(2, Q, nz, nyb, b, nx).permute(2, 3, 0, 1, 4, 5))
         return out
 
     def from_state_layout(self, flat, layout=None):
-        """Flat state-layout buffer -> (2, 19, nz, ny, nx) contiguous copy (cell order)."""
+        """Flat state-layout buffer -> (2, 19, nz, ny, nx) contiguous copy of the
+        population rows (cell order; 16-bit residual rows not included)."""
         nz, ny, nx = self.shape
         v = self.plane_view(flat, layout)                   # (nz, nyb, 2, Q, b, nx)
         rows = v.permute(2, 3, 0, 1, 4, 5).reshape(2, Q, nz, -1, nx)[:, :, :, :ny]

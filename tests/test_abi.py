@@ -102,7 +102,8 @@ def _layout(nx, ny, es):
     if padded % 65536 == 0:
         padded += 256
     s = padded // es
-    return b, s, 38 * s * -(-ny // b)
+    rows = 38 if es == 4 else 40  # the 16-bit forms add the two rest-population residual rows
+    return b, s, rows * s * -(-ny // b)
 
 
 def test_plane_stride_and_state_size(lib):
@@ -150,7 +151,7 @@ def _valid_params(_lib):
     ("tau", (1.0, float("nan")), -1),
     ("G", ((0.5, -1.0), (-1.0, 0.0)), -5),   # self-interaction G^{aa} != 0 (Sec. 2)
     ("storage", 3, -1),
-    ("collision", 2, -1),
+    ("collision", 3, -1),
     ("nx", 0, -1),
     ("rho_wall", (float("inf"), 0.0), -1),
 ])
@@ -178,8 +179,8 @@ def test_invalid_parameters_are_rejected_before_any_device_call(lib, field, valu
 SIZE_CASES = [
     (4096, 3424, 4, 0, True),     # 856 row blocks of 38 * 65,792 B = 2.140e9 B per z plane
     (4096, 3440, 4, 0, False),    # 860 blocks: 2.150e9 >= 2^31
-    (4096, 6880, 4, 1, True),     # 38 * 56.4 MB population planes = 2.142e9 B
-    (4096, 6900, 4, 2, False),
+    (4096, 6552, 4, 1, True),     # 40 rows (38 + 2 residual) of 53.7 MB = 2.147e9 B
+    (4096, 6560, 4, 2, False),
     (1024, 1024, 1023, 0, True),  # N * 4 just below 4 GiB
     (1024, 1024, 1024, 0, False),
     (1024, 1024, 2047, 1, True),  # N just below 2^31
@@ -214,6 +215,7 @@ def test_size_limits_agree_with_init(lib, nx, ny, nz, storage, ok):
 
 def test_status_of_calls_on_a_null_context(lib):
     assert lib.lbm_set_tiling(None, -1, 0) == -1
+    assert lib.lbm_set_block_order(None, 0) == -1
     assert lib.lbm_moments(None, None, None, None, None) == -1
     assert lib.lbm_adjoint_seed(None, None, None) == -1
     assert lib.lbm_destroy(None) == 0

@@ -59,3 +59,29 @@ def test_wall_potential_parameterisation():
     assert abs(a - 0.088) < 1e-15 and b == 0.0          # the paper's 40-degree slug value
     a, b = wall_potential(-0.5, 1.0)
     assert a == 0.0 and b == 0.5
+
+
+def test_meniscus_angle_of_synthetic_arcs():
+    """Circular menisci spanning a channel of height 32 (walls at z = 0.5 and
+    32.5) drawn for a given contact angle through phase A, on either side of
+    the slug, are measured back at that angle."""
+    import math
+    from paper_1601_01237_amd import fits
+    zc, half = 16.5, 16.0
+    zs = np.arange(2.0, 31.0)
+    for theta in (25.0, 40.0, 75.0, 110.0, 140.0):
+        t = math.radians(theta)
+        R = half / abs(math.cos(t))
+        sgn = 1.0 if theta > 90.0 else -1.0  # A at smaller x: bulges into B when non-wetting
+        xc = 64.0 - sgn * R * math.sin(t)
+        xs = xc + sgn * np.sqrt(R * R - (zs - zc) ** 2)
+        for side, x in ((-1, xs), (+1, 128.0 - xs)):  # the mirror meniscus has A on its right
+            # sub-cell crossings of a smooth profile recover the points
+            prof = np.array([[0.5 + side * 0.5 * math.tanh(xx - xz) for xx in range(128)] for xz in x])
+            pts = fits.meniscus_points(np.concatenate([np.zeros((2, 128)), prof]), 0.5, 0, 128,
+                                       range(2, 2 + len(zs)))
+            pts[:, 1] = zs
+            c, r = fits.circle_fit(pts)
+            for zw in (0.5, 32.5):
+                got = fits.meniscus_angle(c, r, zw, side, float(pts[:, 0].mean()))
+                assert abs(got - theta) < 0.5, (theta, side, zw, got)

@@ -294,18 +294,20 @@ def test_adjoint_step_96cube_all_cells(lib, collision, tau):
 
 
 def test_adjoint_workspace_size_and_checks(lib):
-    """The regularized adjoint needs one FP32 state array more workspace; a
-    workspace one byte short, aliased arrays and 16-bit storage are refused
-    before anything is launched."""
+    """The workspace holds three FP64 partial sums per workgroup of the
+    reverse march, whatever the collision; a workspace one byte short,
+    aliased arrays and 16-bit storage are refused before anything is
+    launched."""
     import ctypes
     from paper_1601_01237_amd.sim import Sim
     say("adjoint workspace checks")
     shape = (6, 9, 20)
     rho0 = inputs.sphere_droplet(shape, radius=2.5, seed=3)
     sims = {c: Sim(rho0, tau=(0.8, 0.8), G=-1.0, collision=c) for c in ("bgk", "regularized")}
+    for s in sims.values():
+        s.set_adjoint_tiling(2, 2)  # 32 x 8 tiles, 2-plane chunks: 1 x 2 x 3 workgroups
     wb = {c: int(lib.lbm_adjoint_work_bytes(s.ctx)) for c, s in sims.items()}
-    state_bytes = sims["bgk"].state_elems * 4
-    assert wb["regularized"] - wb["bgk"] == -(-state_bytes // 256) * 256
+    assert wb["regularized"] == wb["bgk"] == 6 * 3 * 8
     s = sims["regularized"]
     lam_in = torch.zeros(s.lam_elems, dtype=torch.float32, device="cuda")
     lam_out = torch.zeros_like(lam_in)
@@ -326,3 +328,42 @@ def test_adjoint_workspace_size_and_checks(lib):
     assert lib.lbm_adjoint_step(h.ctx, p(h.state), p(lam_in), p(lam_out), p(work16),
                                 ctypes.c_size_t(work16.numel()), p(dparams), None) == -5  # LBM_ENOTSUP
     h.close()
+
+
+@pytest.mark.parametrize("collision,walls", [("bgk", False), ("regularized", True)])
+def test_adjoint_tiling_invariance(lib, collision, walls):
+    """Every shape and z chunk of the reverse march gives the same lam_t,
+    bitwise (only the summation order of dL/dG and dL/dtau changes)."""
+    from paper_1601_01237_amd.autograd import Reverse, to_adjoint_layout
+    from paper_1601_01237_amd.sim import Sim
+    shape = (11, 21, 70)
+    say(f"adjoint tiling invariance {collision} walls={walls}")
+    solid = None
+    if walls:
+        solid = np.zeros(shape, bool)
+        solid[0] = True
+        solid[5, 3:9, 20:41] = True
+    f, rho = _random_state(shape, 21, solid)
+    if solid is not None:
+        rho[:, solid] = 0.0
+    sim = Sim(rho, tau=(0.8, 1.2), G=((0.0, -1.3), (-0.7, 0.0)), rho_wall=(0.2, 0.1), solid=solid,
+              collision=collision)
+    sim.set_populations(torch.from_numpy(f.astype(np.float32)))
+    lam1 = np.random.default_rng(22).normal(size=f.shape).astype(np.float32)
+    if solid is not None:
+        lam1[:, :, solid] = 0.0
+    lam_in = to_adjoint_layout(torch.from_numpy(lam1).cuda(), sim)
+    live = sim.live_mask(sim.lam_layout)
+    outs, params = [], []
+    for shp, zc in [(-1, 0), (0, 3), (1, 1), (2, 5), (3, 0), (3, 11)]:
+        sim.set_adjoint_tiling(shp, zc)
+        rev = Reverse(sim)
+        lam, drho = rev.step(sim.state, lam_in, want_drho0=True)
+        torch.cuda.synchronize()
+        outs.append((lam[live].cpu(), drho.cpu()))
+        params.append(rev.dparams.cpu().numpy())
+    sim.close()
+    for lam, drho in outs[1:]:
+        assert torch.equal(lam, outs[0][0]) and torch.equal(drho, outs[0][1])
+    for p in params[1:]:
+        np.testing.assert_allclose(p, params[0], rtol=1e-9, atol=1e-12)

@@ -132,9 +132,10 @@ def test_walls_ragged_with_obstacle(lib):
     sim.close()
 
 
-def _state_after(rho0, p, steps, tile, zchunk, solid=None):
+def _state_after(rho0, p, steps, tile, zchunk, solid=None, order=0):
     sim = _sim(rho0, p, solid=solid)
     sim.set_tiling(tile, zchunk)
+    sim.set_block_order(order)
     sim.step(steps)
     x = sim.state.clone().cpu()
     sim.close()
@@ -158,6 +159,10 @@ def test_tiling_invariance_bitwise(lib, walls):
         got = _state_after(rho0, p, 7, tile, zc, solid)
         diff = float((got - ref).abs().max())
         assert torch.equal(got, ref), (tile, zc, diff)
+    # every block order (lbm_set_block_order), on ragged tiles and chunks
+    for order, tile, zc in [(1, 0, 3), (2, 1, 7), (3, 3, 0), (4, 2, 5), (2, 5, 1), (4, 4, 20)]:
+        got = _state_after(rho0, p, 7, tile, zc, solid, order=order)
+        assert torch.equal(got, ref), (order, tile, zc)
 
 
 def test_run_to_run_determinism(lib):
@@ -207,7 +212,8 @@ def test_checkpoint_resume_bitwise(lib):
                                            ("fp32", (3, 2, 40))])
 def test_march_copy_reference(lib, storage, shape):
     """lbm_march_copy (the bandwidth reference with the step's access
-    pattern) copies every cell of every population plane and nothing else."""
+    pattern) copies every cell of every population plane (and, in the 16-bit
+    forms, of the two residual rows) and nothing else."""
     import ctypes
     import torch
     from paper_1601_01237_amd.sim import Sim
@@ -220,7 +226,8 @@ def test_march_copy_reference(lib, storage, shape):
     assert code == 0
     torch.cuda.synchronize()
     live = sim.live_mask()
-    assert int(live.sum()) == 2 * 19 * sim.n
+    assert int(live.sum()) == sim.layout[2] * sim.n
+    assert sim.layout[2] == (38 if storage == "fp32" else 40)
     assert torch.equal(dst[live], src[live])
     assert bool((dst[~live] == 7.0).all())  # padding untouched
     assert sim.lib.lbm_march_copy(sim.ctx, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(src.data_ptr())) != 0

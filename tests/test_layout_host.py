@@ -26,7 +26,7 @@ def _host_sim(lib, shape, storage):
     """A Sim carrying only the layout attributes (built from the pure host
     queries), enough for its layout helpers on CPU tensors."""
     from paper_1601_01237_amd import _lib
-    from paper_1601_01237_amd.sim import Sim
+    from paper_1601_01237_amd.sim import Sim, layout_rows
     code = {"fp32": _lib.FP32, "fp16": _lib.FP16, "bf16": _lib.BF16}[storage]
     nz, ny, nx = shape
     sim = Sim.__new__(Sim)
@@ -34,9 +34,10 @@ def _host_sim(lib, shape, storage):
     sim.n = nx * ny * nz
     sim.device = torch.device("cpu")
     sim.pstride = int(lib.lbm_plane_stride(nx, ny, code))
-    sim.layout = (int(lib.lbm_row_block(nx, ny, code)), sim.pstride)
+    sim.layout = (int(lib.lbm_row_block(nx, ny, code)), sim.pstride, layout_rows(storage))
     sim.state_elems = int(lib.lbm_state_elems(nx, ny, nz, code))
     sim.row_half = int(lib.lbm_row_half(nx, code, 0))
+    sim.layout_storage = storage
     x = torch.arange(nx)
     h = sim.row_half
     sim.x_pos = torch.where(x < h, 2 * x, 2 * (x - h) + 1) if h else x
@@ -45,9 +46,10 @@ def _host_sim(lib, shape, storage):
 
 def _index(sim, a, i, x, y, z):
     """Flat index of element (a, i, x, y, z) as the header states it."""
-    b, s = sim.layout
+    b, s, rows = sim.layout
     nz, ny, nx = sim.shape
-    zplane = 2 * Q * s * -(-ny // b)
+    assert rows == (2 * Q if sim.layout_storage == "fp32" else 2 * Q + 2)
+    zplane = rows * s * -(-ny // b)
     pos = int(sim.x_pos[x])
     return z * zplane + (y // b) * 2 * Q * s + (a * Q + i) * s + (y % b) * nx + pos
 
@@ -80,8 +82,17 @@ def test_layout_round_trip_and_index_formula(lib, storage, shape):
         x, y, z = int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))
         assert raw[_index(sim, a, i, x, y, z)] == fr[a, i, z, y, x]
     live = sim.live_mask()
-    assert int(live.sum()) == 2 * Q * sim.n
+    assert int(live.sum()) == sim.layout[2] * sim.n
     assert bool((raw[~live] == 0).all())
+    if storage != "fp32":
+        # the residual rows follow the 38 population rows of each plane and
+        # hold zeros after to_state_layout
+        res = sim.residual_view(raw)
+        assert res.shape == (nz, 1, 2, ny, nx) and bool((res == 0).all())
+        res.fill_(7)
+        b, s, rows = sim.layout
+        z, y, x = nz - 1, ny - 1, nx - 1
+        assert raw[z * rows * s + (2 * Q + 1) * s + y * nx + int(sim.x_pos[x])] == 7
 
 
 @pytest.mark.parametrize("storage,shape", CASES)
