@@ -33,7 +33,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {"fp32": 304, "fp16": 156, "bf16": 156}
-ALGO_BYTES_NOTE = "2 species x 19 populations x element size, read + write, per cell-step"
+ADJOINT_BYTES_PER_CELL = 456
+ALGO_BYTES_NOTE = ("2 species x 19 populations x element size (plus the 2 rest-population residuals of the "
+                   "16-bit forms), read + write, per cell-step")
 
 
 def stored_traffic(workload, storage):
@@ -137,9 +139,13 @@ def adjoint_cost(n=96, steps=20, adjoint_tile=None, collision="bgk"):
     torch.cuda.synchronize()
     adj_ms = start.elapsed_time(end) / steps
     sim.close()
+    # one reverse step reads X_t and lam_{t+1} and writes lam_t: 456 B per cell
+    gbs = ADJOINT_BYTES_PER_CELL * n ** 3 / (adj_ms * 1e-3) / 1e9
     return dict(forward_ms=round(fwd_ms, 4), adjoint_step_ms=round(adj_ms, 4),
                 ratio=round(adj_ms / fwd_ms, 3),
-                ratio_with_recompute=round((adj_ms + fwd_ms) / fwd_ms, 3))
+                ratio_with_recompute=round((adj_ms + fwd_ms) / fwd_ms, 3),
+                algorithmic_bytes_per_cell=ADJOINT_BYTES_PER_CELL, gbs=round(gbs, 1),
+                frac=round(gbs / HBM_PEAK_GBS, 4))
 
 
 def copy_ceiling(gib=4.0, reps=10):
@@ -288,6 +294,11 @@ def main():
         r = run_case((192, 192, 384), "fp32", steps_big, 5, rho0=rho_w, solid=solid, tau=0.7, tune=True)
         fluid = int((~solid).sum())
         r["mlups_fluid_only"] = fluid / (r["ms_per_step"] * 1e-3) / 1e6
+        # with walls only fluid cells move populations: the algorithmic bytes
+        # are 304 per fluid cell
+        r["fluid_fraction"] = fluid / r["n"]
+        r["gbs_fluid"] = BYTES_PER_CELL["fp32"] * fluid / (r["ms_per_step"] * 1e-3) / 1e9
+        r["frac_fluid"] = r["gbs_fluid"] / HBM_PEAK_GBS
         extra["384x192x192_walls_fp32"] = _rounded(r)
         print("[bench] adjoint 96^3", file=sys.stderr, flush=True)
         extra["adjoint_96^3"] = adjoint_cost()
@@ -320,6 +331,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "algorithmic_bytes_per_cell": BYTES_PER_CELL["fp32"],
+                     "algorithmic_bytes_note": ALGO_BYTES_NOTE,
                      "copy_ceiling_gbs": round(ceiling, 1),
                      "frac_of_copy_ceiling": round(achieved / ceiling, 4),
                      "pattern_ceiling_gbs": round(pattern, 1),

@@ -275,16 +275,23 @@ lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
  * diagnostics use 64x8.  Host-side setting. */
 lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t tile, int32_t zchunk);
 
-/* Order in which the step kernel's workgroups cover the (z chunk, tile)
- * pairs.  The device deals consecutive workgroups to its 8 XCDs in turn and
- * the kernel renumbers them so that each XCD (with its own L2 cache) runs a
- * contiguous range of the order; the order therefore decides which tiles
- * share an L2 while they run.  1 = chunk by chunk, tiles x fastest; 2 =
- * chunk by chunk, tiles y fastest; 3 = tile by tile (x fastest), every chunk
- * of a tile together; 4 = as 3 with tiles y fastest; 0 (the default) = 3 with
- * walls, 1 without.  Results do not depend on this choice (bitwise).
- * LBM_EINVAL outside 0..4.  Host-side setting. */
-lbm_status lbm_set_block_order(lbm_ctx *ctx, int32_t order);
+/* Placement of the step kernel's workgroups (results do not depend on it,
+ * bitwise; host-side setting).
+ *   order: the order in which workgroups cover the (z chunk, tile) pairs.
+ *     The device deals consecutive workgroups to its 8 XCDs in turn and the
+ *     kernel renumbers them so that each XCD (with its own L2 cache) runs a
+ *     contiguous range of the order, so the order decides which tiles share
+ *     an L2 while they run.  1 = chunk by chunk, tiles x fastest; 2 = chunk
+ *     by chunk, tiles y fastest; 3 = tile by tile (x fastest), every chunk
+ *     of a tile together; 4 = as 3 with tiles y fastest; 0 (the default) = 3
+ *     with walls, 1 without.
+ *   x_offset: the tile grid of the single-cell shapes (0..5) is shifted by
+ *     this many cells in x, wrapping around the periodic x axis (the tile
+ *     starting at x_offset); -1 (the default) takes 32 (128 bytes) for FP32
+ *     rows of at least 64 cells and 0 otherwise.  The paired shapes ignore
+ *     it.
+ * LBM_EINVAL for order outside 0..4 or x_offset outside -1..nx-1. */
+lbm_status lbm_set_placement(lbm_ctx *ctx, int32_t order, int32_t x_offset);
 
 /* ---- Adjoint (reverse mode) of one step, FP32 storage -------------------
  * (16-bit storage forms and LBM_REGULARIZED3: LBM_ENOTSUP).  BGK (Eq. 2)

@@ -443,6 +443,7 @@ hipError_t launch_variant(const Grid& g, const Phys& ph, const Tiling& t, const 
 Tiling adjoint_march_tiling(const Grid& g, int shape, int zchunk) {
   Tiling t{};
   t.order = ORDER_PLANE_X;
+  t.xoff = 0;
   if (shape < 0 || shape >= ADJOINT_SHAPES) {
     t.blocks = -1;
     return t;

@@ -28,6 +28,7 @@ struct lbm_ctx {
   int device;          // HIP device current at lbm_init
   int adj_shape, adj_zchunk;  // tiling of the reverse march (-1 / 0: automatic)
   int order;           // block order of the step kernel (0: automatic)
+  int xoff;            // x shift of the step kernel's tile grid (-1: automatic)
 };
 
 // Partial sums of lbm_moments_static: a fixed array in device memory, one
@@ -74,6 +75,15 @@ lbm_status from_hip(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EHIP; 
 // each XCD takes every chunk of a run of tiles, which keeps the XCDs evenly
 // loaded (measured: 5% on the inclined channel, 2% slower on open boxes).
 int default_order(const lbm_ctx* c) { return c->links ? ORDER_TILE_X : ORDER_PLANE_X; }
+// Automatic x shift of the tile grid: 32 cells (128 bytes) for FP32 rows of
+// at least 64 cells, else none.  Measured with the automatic tiles: 128^3
+// 131.2 -> 129.1 us, 512^3 8.06 -> 7.92 ms, and with the tuned 64 x 12 tiles
+// on the 384 x 192 x 192 inclined channel 0.858 -> 0.798 ms; shifts of 8 or
+// 16 cells (rows no longer 128-byte aligned) were slower than none.
+int default_xoff(const lbm_ctx* c, const Tiling& t) {
+  if (pair_shape(t.tile) || c->storage != Storage::F32 || c->g.nx < 64) return 0;
+  return 32;
+}
 
 // Step kernel: the selected tile shape (automatic: 128x4 without walls, 64x8
 // with walls, the faster of the shapes measured on each); diagnostics: shape 0.
@@ -87,6 +97,7 @@ Tiling step_tiling(const lbm_ctx* c) {
   if (c->tile < 0 && open_box && c->storage == Storage::F32 && t.blocks > 0 && t.blocks <= 128)
     t = make_tiling(c->g, 4, c->zchunk, open_box);
   t.order = c->order > 0 ? c->order : default_order(c);
+  t.xoff = c->xoff >= 0 ? c->xoff : default_xoff(c, t);
   return t;
 }
 Tiling aux_tiling(const lbm_ctx* c) {
@@ -239,6 +250,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
   c->adj_shape = -1;
   c->adj_zchunk = 0;
   c->order = 0;
+  c->xoff = -1;
   c->device = -1;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
@@ -366,9 +378,10 @@ lbm_status lbm_set_tiling(lbm_ctx* c, int32_t tile, int32_t zchunk) {
   return LBM_OK;
 }
 
-lbm_status lbm_set_block_order(lbm_ctx* c, int32_t order) {
-  if (!c || order < 0 || order > BLOCK_ORDERS) return LBM_EINVAL;
+lbm_status lbm_set_placement(lbm_ctx* c, int32_t order, int32_t x_offset) {
+  if (!c || order < 0 || order > BLOCK_ORDERS || x_offset < -1 || x_offset >= c->g.nx) return LBM_EINVAL;
   c->order = order;
+  c->xoff = x_offset;
   return LBM_OK;
 }
 

@@ -74,6 +74,7 @@ struct Tiling {
   int tiles_x, tiles_y, tiles_z;
   int blocks;
   int order;     // BlockOrder
+  int xoff;      // x of the first tile's first column (the tile grid is shifted, wrapping in x)
 };
 
 struct TileCoord {

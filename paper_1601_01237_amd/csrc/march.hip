@@ -86,7 +86,11 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
   // Which tile and z chunk: the launch's block order (launch.h).
   const TileCoord tc = tile_of_block(b, tl);
   const int bxx = tc.x, byy = tc.y, bz = tc.z;
-  const int x0 = bxx * BXT, y0 = byy * ROWS, z0 = bz * tl.zchunk;
+  // The tile grid may be shifted in x by tl.xoff cells (wrapping): tile
+  // column bxx covers x = bxx * BXT + xoff + tx (mod nx); the lane owns its
+  // cell when the unshifted column bxx * BXT + tx lies inside the grid.
+  const int lx0 = bxx * BXT;
+  const int x0 = lx0 + tl.xoff, y0 = byy * ROWS, z0 = bz * tl.zchunk;
   const int z1 = min(z0 + tl.zchunk, g.nz);
   const int kmax = z1 - z0 + 1;  // planes p_k = z0 - 1 + k for k = 0..kmax
 
@@ -110,7 +114,7 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
     // ------------------------------------------------------------ own waves
     const int tx = tid % BXT, ty = tid / BXT;
     const int ex = x0 + tx, ey = y0 + ty;
-    const bool owner = ex < g.nx && ey < g.ny;  // ragged edge lanes only feed the ring
+    const bool owner = lx0 + tx < g.nx && ey < g.ny;  // ragged edge lanes only feed the ring
     const Column col = make_column<T>(ex, ey, g);
     const uint32_t col_b = col.y[1] + col.x[1];
     const uint32_t col_off = col.cell;
@@ -350,6 +354,7 @@ static int round_chunk(long long txy, int nz, long long cap) {
 Tiling make_tiling(const Grid& g, int tile, int zchunk, bool open_box) {
   Tiling t{};
   t.order = ORDER_PLANE_X;
+  t.xoff = 0;
   if (tile < 0 || tile >= NTILES) {
     t.blocks = -1;
     return t;

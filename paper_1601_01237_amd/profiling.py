@@ -120,7 +120,7 @@ def cmd_run(args):
     sim = Sim(**kw)
     if args.zchunk or args.tile >= 0:
         sim.set_tiling(args.tile, args.zchunk)
-    sim.set_block_order(args.order)
+    sim.set_placement(args.order, args.xoff)
     if args.march_copy:
         # the step's access pattern without arithmetic, on a copy of the state
         dst = torch.empty_like(sim.state)
@@ -269,6 +269,36 @@ def _kernel_class(name):
     return None
 
 
+XCDS, CUS, SIMDS = 8, 256, 1024
+
+
+def _derived(m):
+    """Ratios that name a bound, from the mean counters of one kernel."""
+    out = []
+    cyc = m.get("GRBM_GUI_ACTIVE", 0.0) / XCDS  # cycles of the dispatch (per XCD)
+    if cyc > 0:
+        out.append(f"{cyc:.4g} cycles")
+        if "SQ_ACTIVE_INST_VALU" in m:
+            out.append(f"VALU busy {100.0 * m['SQ_ACTIVE_INST_VALU'] * 4 / SIMDS / cyc:.1f}%")
+        if "TA_ADDR_STALLED_BY_TC_CYCLES_sum" in m:
+            out.append(f"TA address stalled by L1 {100.0 * m['TA_ADDR_STALLED_BY_TC_CYCLES_sum'] / CUS / cyc:.1f}%")
+        if "TA_DATA_STALLED_BY_TC_CYCLES_sum" in m:
+            out.append(f"TA data stalled by L1 {100.0 * m['TA_DATA_STALLED_BY_TC_CYCLES_sum'] / CUS / cyc:.1f}%")
+        if "TCP_PENDING_STALL_CYCLES_sum" in m:
+            out.append(f"L1 pending stall {100.0 * m['TCP_PENDING_STALL_CYCLES_sum'] / CUS / cyc:.1f}%")
+        if "TCP_TCC_READ_REQ_LATENCY_sum" in m:
+            out.append(f"L1->L2 reads in flight {m['TCP_TCC_READ_REQ_LATENCY_sum'] / cyc:.4g}")
+        if "TCP_TCC_READ_REQ_sum" in m:
+            out.append(f"L1->L2 read requests/cycle {m['TCP_TCC_READ_REQ_sum'] / cyc:.3g}")
+    if m.get("TCP_TCC_READ_REQ_sum", 0.0) > 0 and "TCP_TCC_READ_REQ_LATENCY_sum" in m:
+        out.append(f"mean L1->L2 read latency {m['TCP_TCC_READ_REQ_LATENCY_sum'] / m['TCP_TCC_READ_REQ_sum']:.0f} cycles")
+    if m.get("TCC_HIT_sum", 0.0) + m.get("TCC_MISS_sum", 0.0) > 0:
+        out.append(f"L2 hit rate {100.0 * m['TCC_HIT_sum'] / (m['TCC_HIT_sum'] + m['TCC_MISS_sum']):.1f}%")
+    if m.get("SQ_WAVE_CYCLES", 0.0) > 0 and "SQ_WAIT_INST_ANY" in m:
+        out.append(f"waves waiting on an instruction {100.0 * m['SQ_WAIT_INST_ANY'] / m['SQ_WAVE_CYCLES']:.1f}% of wave cycles")
+    return out
+
+
 def cmd_counters(args):
     """Mean per dispatch of every counter in one or more counter_collection.csv
     files, for the reference copy, the pattern copy and the step kernel."""
@@ -291,6 +321,12 @@ def cmd_counters(args):
             v = table.get((name, c))
             cells.append(f"{sum(v) / len(v):18.6g}" if v else f"{'-':>18}")
         lines.append(f"{name:32} " + " ".join(cells))
+    lines += ["", "derived (per dispatch; the GRBM counter is summed over the 8 XCDs, the TA/TCP ones over the",
+              "256 CUs, SQ_ACTIVE_INST_VALU counts 4-cycle issue slots over the 1024 SIMDs):"]
+    for c in classes:
+        d = _derived({name: sum(v) / len(v) for (name, cls), v in table.items() if cls == c})
+        if d:
+            lines.append(f"  {c}: " + "; ".join(d))
     for note in args.note or ():
         lines.append(note)
     with open(args.out, "w") as f:
@@ -331,7 +367,8 @@ def main(argv=None):
     r.add_argument("--copy-reps", type=int, default=3)
     r.add_argument("--zchunk", type=int, default=0, help="z planes per workgroup (0 = the library's default)")
     r.add_argument("--tile", type=int, default=-1, help="tile shape (-1 = automatic)")
-    r.add_argument("--order", type=int, default=0, help="block order (0 = automatic, see lbm_set_block_order)")
+    r.add_argument("--order", type=int, default=0, help="block order (0 = automatic, see lbm_set_placement)")
+    r.add_argument("--xoff", type=int, default=-1, help="x shift of the tile grid (-1 = automatic)")
     r.add_argument("--march-copy", type=int, default=0,
                    help="launches of lbm_march_copy (the step's access pattern) before the steps")
     ra = sub.add_parser("run-adjoint")

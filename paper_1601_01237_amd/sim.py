@@ -183,31 +183,32 @@ class Sim:
         _lib.check("lbm_set_tiling", self.lib.lbm_set_tiling(self.ctx, int(tile), int(zchunk)))
         self.tiling = (int(tile), int(zchunk))
 
-    def set_block_order(self, order=0):
-        """Order of the step kernel's workgroups over (z chunk, tile) (0 = automatic, 1..4, see
-        lbm_set_block_order)."""
-        _lib.check("lbm_set_block_order", self.lib.lbm_set_block_order(self.ctx, int(order)))
+    def set_placement(self, order=0, x_offset=-1):
+        """Placement of the step kernel's workgroups: their order over (z chunk, tile) (0 = automatic,
+        1..4) and the x shift of the tile grid (-1 = automatic); see lbm_set_placement."""
+        _lib.check("lbm_set_placement", self.lib.lbm_set_placement(self.ctx, int(order), int(x_offset)))
 
     def set_adjoint_tiling(self, shape=-1, zchunk=0):
         """Tile shape of the reverse march (-1 = automatic, 0..3, see
         lbm_set_adjoint_tiling) and z planes per workgroup (0 = default)."""
         _lib.check("lbm_set_adjoint_tiling", self.lib.lbm_set_adjoint_tiling(self.ctx, int(shape), int(zchunk)))
 
-    def tune(self, zchunks=(0, 8, 12, 16, 24, 32, 48, 64), tiles=(-1,), steps=None, orders=(0,)):
-        """Time the step for every (tile shape, z chunk, block order) of
-        ``tiles`` x ``zchunks`` x ``orders`` (tile -1 = the library's automatic
-        shape, zchunk 0 = its default chunk, order 0 = its default order; see
-        lbm_set_tiling and lbm_set_block_order) and keep the fastest.  The
-        state and time level are restored afterwards (bitwise: every tiling
-        computes the same step), so tuning can precede any run.  Shapes the
-        context cannot run (pair shapes on unfolded rows, for instance) are
-        skipped.  Returns (tile, zchunk, {(tile, zchunk[, order]): ms per
-        step}); the keys carry the order only when more than one is tried,
-        and the chosen order stays set."""
+    def tune(self, zchunks=(0, 8, 12, 16, 24, 32, 48, 64), tiles=(-1,), steps=None, placements=((0, -1),)):
+        """Time the step for every (tile shape, z chunk, placement) of
+        ``tiles`` x ``zchunks`` x ``placements`` (tile -1 = the library's
+        automatic shape, zchunk 0 = its default chunk, placement (0, -1) = its
+        default order and x shift; see lbm_set_tiling and lbm_set_placement)
+        and keep the fastest.  The state and time level are restored
+        afterwards (bitwise: every tiling computes the same step), so tuning
+        can precede any run.  Shapes the context cannot run (pair shapes on
+        unfolded rows, for instance) are skipped.  Returns (tile, zchunk,
+        {(tile, zchunk[, placement]): ms per step}); the keys carry the
+        placement only when more than one is tried, and the chosen placement
+        stays set."""
         import torch
         nz = self.shape[0]
         cands = [z for z in dict.fromkeys(int(z) for z in zchunks) if z <= nz]
-        order_list = list(dict.fromkeys(int(o) for o in orders))
+        place_list = list(dict.fromkeys((int(o), int(x)) for o, x in placements))
         n = int(steps) if steps else max(2, min(20, int(4e8 // self.n)))
         ckpt = self.checkpoint()
 
@@ -226,8 +227,8 @@ class Sim:
         while spent < 50.0:
             spent += timed(n)
         times = {}
-        for order in order_list:
-            self.set_block_order(order)
+        for place in place_list:
+            self.set_placement(*place)
             for tile in dict.fromkeys(int(t) for t in tiles):
                 for z in cands:
                     try:
@@ -235,14 +236,14 @@ class Sim:
                     except _lib.LBMError:
                         break
                     self.step(1)
-                    key = (tile, z, order) if len(order_list) > 1 else (tile, z)
+                    key = (tile, z, place) if len(place_list) > 1 else (tile, z)
                     times[key] = min(timed(n), timed(n)) / n  # best of two
         self.restore(ckpt)
         if not times:
             raise ValueError("no tiling of the candidates runs on this grid")
         best = min(times, key=times.get)
         self.set_tiling(best[0], best[1])
-        self.set_block_order(best[2] if len(best) > 2 else order_list[0])
+        self.set_placement(*(best[2] if len(best) > 2 else place_list[0]))
         return best[0], best[1], times
 
     @property

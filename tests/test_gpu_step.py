@@ -132,10 +132,10 @@ def test_walls_ragged_with_obstacle(lib):
     sim.close()
 
 
-def _state_after(rho0, p, steps, tile, zchunk, solid=None, order=0):
+def _state_after(rho0, p, steps, tile, zchunk, solid=None, place=(0, -1)):
     sim = _sim(rho0, p, solid=solid)
     sim.set_tiling(tile, zchunk)
-    sim.set_block_order(order)
+    sim.set_placement(*place)
     sim.step(steps)
     x = sim.state.clone().cpu()
     sim.close()
@@ -159,10 +159,12 @@ def test_tiling_invariance_bitwise(lib, walls):
         got = _state_after(rho0, p, 7, tile, zc, solid)
         diff = float((got - ref).abs().max())
         assert torch.equal(got, ref), (tile, zc, diff)
-    # every block order (lbm_set_block_order), on ragged tiles and chunks
-    for order, tile, zc in [(1, 0, 3), (2, 1, 7), (3, 3, 0), (4, 2, 5), (2, 5, 1), (4, 4, 20)]:
-        got = _state_after(rho0, p, 7, tile, zc, solid, order=order)
-        assert torch.equal(got, ref), (order, tile, zc)
+    # every block order and x shifts of the tile grid (lbm_set_placement),
+    # on ragged tiles and chunks
+    for place, tile, zc in [((1, 0), 0, 3), ((2, 5), 1, 7), ((3, 16), 3, 0), ((4, 69), 2, 5), ((2, 1), 5, 1),
+                            ((4, 33), 4, 20), ((0, 16), 0, 0), ((1, 63), 1, 2)]:
+        got = _state_after(rho0, p, 7, tile, zc, solid, place=place)
+        assert torch.equal(got, ref), (place, tile, zc)
 
 
 def test_run_to_run_determinism(lib):
