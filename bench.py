@@ -32,7 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_CELL = {"fp32": 304, "fp16": 156, "bf16": 156}
+BYTES_PER_CELL = {"fp32": 304, "fp16": 160, "bf16": 160}
 ADJOINT_BYTES_PER_CELL = 456
 ALGO_BYTES_NOTE = ("2 species x 19 populations x element size (plus the 2 rest-population residuals of the "
                    "16-bit forms), read + write, per cell-step")

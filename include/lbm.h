@@ -317,9 +317,9 @@ size_t lbm_adjoint_work_bytes(const lbm_ctx *ctx);
  * summation order of dparams): shape 0 = 64x8, 1 = 32x16, 2 = 32x8, 3 = 64x4
  * cells, or -1 (the default) for the automatic choice -- 32x8 or 64x4,
  * whichever pads the x-y plane less; zchunk = z planes per workgroup, 0 =
- * the default, which minimises
- * (rounds of 256 workgroups) x (zchunk + 5).  lbm_adjoint_work_bytes follows
- * this setting.  Host-side setting; LBM_EINVAL outside these ranges. */
+ * the default, which minimises (rounds of 256 workgroups) x (zchunk + 5).
+ * lbm_adjoint_work_bytes follows this setting.  Host-side setting;
+ * LBM_EINVAL outside these ranges. */
 lbm_status lbm_set_adjoint_tiling(lbm_ctx *ctx, int32_t shape, int32_t zchunk);
 lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *x_t, const float *lam_in,
                             float *lam_out, void *work, size_t work_bytes,

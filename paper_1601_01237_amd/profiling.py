@@ -40,26 +40,35 @@ import ctypes
 import hashlib
 import json
 import os
+import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-# the step kernel, the reverse march and the launch choices (api.hip)
-KERNEL_SOURCES = ("march.hip", "march_pair.hip", "adjoint_march.hip", "adjoint_cell.h", "pull.h", "cell.h", "buffer.h",
-                  "lattice.h", "launch.h", "api.hip")
-BYTES_PER_CELL = {"fp32": 304, "fp16": 156, "bf16": 156}
+# Sources each kernel is built from, with the launch choices (api.hip).
+COMMON_SOURCES = ("pull.h", "cell.h", "buffer.h", "lattice.h", "launch.h", "api.hip")
+KERNEL_SOURCES = {"step": ("march.hip", "march_pair.hip") + COMMON_SOURCES,
+                  "reverse": ("adjoint_march.hip", "adjoint_cell.h") + COMMON_SOURCES}
+BYTES_PER_CELL = {"fp32": 304, "fp16": 160, "bf16": 160}
 SHAPES = {"128": (128, 128, 128), "512": (512, 512, 512), "walls": (192, 192, 384), "adjoint96": (96, 96, 96)}
 # Algorithmic bytes per cell of one reverse step: X_t and lam_{t+1} read once,
 # lam_t written once (FP32).
 ADJOINT_BYTES_PER_CELL = 456
 
 
-def kernel_source_hash():
-    """Hash of the sources the step kernel is built from."""
+def _code_only(text):
+    """Source text without comments and blank space (comment edits keep the hash)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(kind="step"):
+    """Hash of the code (comments removed) of the sources a kernel is built from."""
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(HERE, "csrc", name), "rb") as f:
-            h.update(f.read())
+    for name in KERNEL_SOURCES[kind]:
+        with open(os.path.join(HERE, "csrc", name)) as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -206,7 +215,7 @@ def cmd_traffic(args):
         fluid = int((~kw["solid"]).sum())
     algo_fluid = BYTES_PER_CELL[args.storage] * fluid
     entry = {
-        "kernel_hash": kernel_source_hash(),
+        "kernel_hash": kernel_source_hash("reverse" if pick is _is_adjoint else "step"),
         "bytes_per_launch": round(rd + wr),
         "read_bytes_per_launch": round(rd),
         "write_bytes_per_launch": round(wr),

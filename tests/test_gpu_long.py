@@ -132,20 +132,25 @@ def test_long_horizon_fp32_parity(name):
 @pytest.mark.parametrize("storage", ["fp16", "bf16"])
 def test_persistent_droplet_16bit_storage(storage):
     """The 16-bit storage forms on the droplet that persists for all 2000
-    steps, against the FP64 oracle: FP16 holds rho within 1e-2 of it and the
-    species masses within 1e-2 (the storage tolerance); BF16 (unit roundoff
-    2^-8) is reported against the same figures and only held to 5e-2.  The
+    steps, against the FP64 oracle: FP16 holds rho within 1e-2 of it (the
+    storage tolerance); BF16 (unit roundoff 2^-8) is reported against the
+    same figure and only held to 5e-2.  The species masses stay within 1e-6
+    (FP16) and 2e-4 (BF16) of the initial ones at every stored step: the
+    stored rest population carries its rounding residual, so the mass moves
+    only by the initial rounding and not by a random walk over the steps
+    (measured: 3.1e-7 and 5.0e-5, constant from the first step).  The
     error, u_F error and mass drift are printed against the step count."""
     name = "droplet_48cube_g26"
     say(f"long-horizon {name} {storage}")
     g, solid, region, out = _run(name, storage)
     mass0 = g["mass0"]
     tol = 1e-2 if storage == "fp16" else 5e-2
+    tol_mass = 1e-6 if storage == "fp16" else 2e-4
     for t, rho, uf, d in out:
         e_rho, e_u = _errors(g, t, rho, uf)
         drift = max(abs(d["mass_a"] - mass0[0]) / mass0[0], abs(d["mass_b"] - mass0[1]) / mass0[1])
         print(f"[long] {name} {storage} t={t}: rho {e_rho:.2e}, u_F/max|u_F| {e_u:.2e}, mass drift {drift:.2e}")
-        assert e_rho <= tol and drift <= tol, (storage, t, e_rho, drift)
+        assert e_rho <= tol and drift <= tol_mass, (storage, t, e_rho, drift)
     t, rho, uf, d = out[-1]
     ref_rho = g["rho"].astype(np.float64)
     e_rho = max(np.max(np.abs(rho[a] - ref_rho[a])) / np.max(np.abs(ref_rho[a])) for a in range(2))
