@@ -113,8 +113,12 @@ def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1
 def adjoint_cost(n=96, steps=20, adjoint_tile=None, collision="bgk"):
     """Forward step vs one reverse step on the differentiation workload (n^3, R = 20 n / 96).
 
-    Both at the library's automatic tiling unless ``adjoint_tile`` names the
-    adjoint march's shape (0, 2 or 4); ``collision`` is the operator of both."""
+    The reverse sweep recomputes each forward step with lbm_step_fields
+    (the step plus the densities and velocity the reverse step reads) and
+    runs lbm_adjoint_step_fields; the reverse step that pulls those itself
+    (lbm_adjoint_step) is timed too.  Both at the library's automatic tiling
+    unless ``adjoint_tile`` names the reverse march's shape; ``collision`` is
+    the operator of both."""
     import torch
     from paper_1601_01237_amd import inputs
     from paper_1601_01237_amd.autograd import Reverse
@@ -123,27 +127,44 @@ def adjoint_cost(n=96, steps=20, adjoint_tile=None, collision="bgk"):
     sim = Sim(rho0, tau=(1.0, 1.0), G=-1.0, collision=collision)
     fwd_ms = time_steps(sim, steps, 5)[0]
     if adjoint_tile is not None:
-        sim.set_tiling(adjoint_tile, 0)
+        sim.set_adjoint_tiling(adjoint_tile, 0)
+    fields = torch.empty(5 * n ** 3, dtype=torch.float32, device=sim.device)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(sim.stream)
+        for _ in range(steps):
+            fn()
+        end.record(sim.stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(end) / steps
+
+    x_t = sim.state.clone()
+    fwd_fields_ms = timed(lambda: sim.step_fields(fields))
+    # fields of x_t (the state the reverse steps below differentiate at)
+    sim.restore((x_t, sim.t))
+    sim.step_fields(fields)
     rev = Reverse(sim)
     grad = torch.ones((2, n, n, n), dtype=torch.float32, device=sim.device)
-    lam = rev.seed(grad)
-    x_t = sim.state.clone()
-    lam, _ = rev.step(x_t, lam)
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record(sim.stream)
-    for _ in range(steps):
-        lam, _ = rev.step(x_t, lam)
-    end.record(sim.stream)
-    torch.cuda.synchronize()
-    adj_ms = start.elapsed_time(end) / steps
+    lam0 = rev.seed(grad)
+    box = {"lam": lam0}
+
+    def rstep(f):
+        box["lam"], _ = rev.step(x_t, box["lam"], fields=f)
+
+    adj_ms = timed(lambda: rstep(fields))
+    box["lam"] = lam0
+    adj_pull_ms = timed(lambda: rstep(None))
     sim.close()
     # one reverse step reads X_t and lam_{t+1} and writes lam_t: 456 B per cell
     gbs = ADJOINT_BYTES_PER_CELL * n ** 3 / (adj_ms * 1e-3) / 1e9
-    return dict(forward_ms=round(fwd_ms, 4), adjoint_step_ms=round(adj_ms, 4),
+    return dict(forward_ms=round(fwd_ms, 4), forward_fields_ms=round(fwd_fields_ms, 4),
+                adjoint_step_ms=round(adj_ms, 4), adjoint_step_pull_ms=round(adj_pull_ms, 4),
                 ratio=round(adj_ms / fwd_ms, 3),
-                ratio_with_recompute=round((adj_ms + fwd_ms) / fwd_ms, 3),
+                ratio_with_recompute=round((adj_ms + fwd_fields_ms) / fwd_ms, 3),
                 algorithmic_bytes_per_cell=ADJOINT_BYTES_PER_CELL, gbs=round(gbs, 1),
                 frac=round(gbs / HBM_PEAK_GBS, 4))
 

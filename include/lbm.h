@@ -208,6 +208,17 @@ lbm_status lbm_init(lbm_ctx **ctx, const lbm_params *p, void *buf_a, void *buf_b
  * stream with bounce-back); t += n.  One fused kernel launch per step. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
 
+/* One step, as lbm_step(ctx, 1), that also writes the forward quantities
+ * the reverse step at this time level needs (Eqs. 4-6 at the pull of X_t):
+ * fields (device float, 5*N, caller-owned, index k*N + c) receives
+ * rho~^A, rho~^B, u_x, u_y, u_z of every cell c, with rho~^a = rho_s^a and
+ * u = 0 on wall cells.  Passed to lbm_adjoint_step_fields with the same X_t,
+ * it replaces the reverse march's own pull of the tile border.  FP32
+ * storage and the BGK or second-order regularized collision only
+ * (LBM_ENOTSUP otherwise); fields must not alias a state buffer
+ * (LBM_EINVAL).  t += 1. */
+lbm_status lbm_step_fields(lbm_ctx *ctx, float *fields);
+
 /* Observables of the current time t (Eqs. 4-9).  Any output may be NULL.
  *   rho    device float, 2*N: rho^a(c) at a*N + c (0 on solid cells).
  *   u_f    device float, 3*N: component k of u_F at k*N + c (0 on solid).
@@ -324,6 +335,15 @@ lbm_status lbm_set_adjoint_tiling(lbm_ctx *ctx, int32_t shape, int32_t zchunk);
 lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *x_t, const float *lam_in,
                             float *lam_out, void *work, size_t work_bytes,
                             double *dparams, double *drho0);
+
+/* lbm_adjoint_step with the forward quantities of X_t read from fields (5*N
+ * floats written by the lbm_step_fields call that advanced X_t) instead of
+ * pulled again from X_t for the tile and its two-cell border: the same
+ * results, bitwise, with less traffic.  fields must not alias x_t, lam_in or
+ * lam_out (LBM_EINVAL); NULL fields: LBM_EINVAL. */
+lbm_status lbm_adjoint_step_fields(lbm_ctx *ctx, const void *x_t, const float *fields,
+                                   const float *lam_in, float *lam_out, void *work,
+                                   size_t work_bytes, double *dparams, double *drho0);
 
 /* dL/dX_T for an objective of the densities at time T: given
  * grad_rho (device float, 2*N, index a*N + c) = dL/drho^a(x, T), writes lam

@@ -8,9 +8,11 @@ dL/drho0 (float64, same shape), dL/dG (tied G^{AB} = G^{BA}) and dL/dtau
 
 Backward is a checkpointed reverse sweep: the forward pass keeps the stored
 state every ``every`` steps; for each segment, last first, the states of the
-segment are recomputed from its checkpoint and the library's adjoint step
-(transposed collision with the Eq. (7) gather, transposed pull streaming)
-carries dL/dX_{t+1} back to dL/dX_t.  All of it runs in liblbm.so.
+segment are recomputed from its checkpoint (each recomputed step also writes
+the densities and mixture velocity of the state it starts from) and the
+library's adjoint step (transposed collision with the Eq. (7) gather,
+transposed pull streaming) carries dL/dX_{t+1} back to dL/dX_t.  All of it
+runs in liblbm.so.
 """
 
 from __future__ import annotations
@@ -52,15 +54,23 @@ class Reverse:
         _lib.check("lbm_adjoint_seed", self.lib.lbm_adjoint_seed(self.sim.ctx, _ptr(g), _ptr(lam)))
         return lam
 
-    def step(self, x_t, lam_next, want_drho0=False):
-        """dL/dX_t from dL/dX_{t+1}; accumulates into self.dparams."""
+    def step(self, x_t, lam_next, want_drho0=False, fields=None):
+        """dL/dX_t from dL/dX_{t+1}; accumulates into self.dparams.  With
+        ``fields`` (from ``Sim.step_fields`` at X_t) the reverse march reads
+        the forward densities and velocity instead of pulling X_t again
+        (same results, bitwise)."""
         lam = torch.empty_like(lam_next)
         drho0 = None
         if want_drho0:
             drho0 = torch.empty(2 * self.sim.n, dtype=torch.float64, device=self.sim.device)
-        _lib.check("lbm_adjoint_step", self.lib.lbm_adjoint_step(
-            self.sim.ctx, _ptr(x_t), _ptr(lam_next), _ptr(lam), _ptr(self.work),
-            C.c_size_t(self.work.numel()), _ptr(self.dparams), _ptr(drho0)))
+        if fields is None:
+            _lib.check("lbm_adjoint_step", self.lib.lbm_adjoint_step(
+                self.sim.ctx, _ptr(x_t), _ptr(lam_next), _ptr(lam), _ptr(self.work),
+                C.c_size_t(self.work.numel()), _ptr(self.dparams), _ptr(drho0)))
+        else:
+            _lib.check("lbm_adjoint_step_fields", self.lib.lbm_adjoint_step_fields(
+                self.sim.ctx, _ptr(x_t), _ptr(fields), _ptr(lam_next), _ptr(lam), _ptr(self.work),
+                C.c_size_t(self.work.numel()), _ptr(self.dparams), _ptr(drho0)))
         return lam, drho0
 
 
@@ -83,12 +93,15 @@ def reverse_sweep(sim: Sim, ckpts, steps: int, every: int, grad_rho):
     for s in reversed(starts):
         e = min(s + every, steps)
         sim.restore((ckpts[s], s))
-        states = [ckpts[s]]
-        for _ in range(s + 1, e):
-            sim.step(1)
+        # recompute the segment: X_s .. X_{e-1}, and with each step the
+        # forward fields of the state it started from (the step to X_e
+        # gives those of X_{e-1})
+        states, fields = [], []
+        for _ in range(s, e):
             states.append(sim.state.clone())
+            fields.append(sim.step_fields())
         for t in range(e - 1, s - 1, -1):
-            lam, d = rev.step(states[t - s], lam, want_drho0=(t == 0))
+            lam, d = rev.step(states[t - s], lam, want_drho0=(t == 0), fields=fields[t - s])
             if d is not None:
                 drho0 = d
     d = rev.dparams.cpu()

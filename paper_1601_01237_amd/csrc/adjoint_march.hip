@@ -103,7 +103,17 @@ __device__ __forceinline__ void pull_moments(const __amdgpu_buffer_rsrc_t rz[3],
   mixture_velocity(f, d[0] + d[1], u);
 }
 
-template <bool WALLS, bool REG, int BXT, int ROWS, int HW>
+// The same quantities from the fields a forward step wrote (Mode::StepFields):
+// bitwise what pull_moments gives for the cell.
+__device__ __forceinline__ void read_fields(const float* __restrict__ fields, uint32_t c, uint64_t n, float2& r,
+                                            float u[3]) {
+  r = make_float2(fields[c], fields[n + c]);
+  u[0] = fields[2 * n + c];
+  u[1] = fields[3 * n + c];
+  u[2] = fields[4 * n + c];
+}
+
+template <bool WALLS, bool REG, bool FIELDS, int BXT, int ROWS, int HW>
 __global__ void __launch_bounds__(BXT * ROWS + 64 * HW)
 adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const AdjointIO io) {
   using Sh = AdjShape<BXT, ROWS, HW>;
@@ -163,13 +173,17 @@ adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const Adjoint
         lk_a = WALLS ? io.links[static_cast<uint32_t>(zw) * g.nxy + col.cell] : 0u;
         float2 r = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
         if (!(WALLS && (lk_a & 1u))) {
-          __amdgpu_buffer_rsrc_t rz[3];
-          rz[0] = plane_rsrc<float>(io.x_t, wrap(p - 1, g.nz), g);
-          rz[1] = plane_rsrc<float>(io.x_t, zw, g);
-          rz[2] = plane_rsrc<float>(io.x_t, wrap(p + 1, g.nz), g);
-          float rho[2];
-          pull_moments<WALLS>(rz, ppb, col, lk_a, rho, u_a);
-          r = make_float2(rho[0], rho[1]);
+          if constexpr (FIELDS) {
+            read_fields(io.fields, static_cast<uint32_t>(zw) * g.nxy + col.cell, g.n, r, u_a);
+          } else {
+            __amdgpu_buffer_rsrc_t rz[3];
+            rz[0] = plane_rsrc<float>(io.x_t, wrap(p - 1, g.nz), g);
+            rz[1] = plane_rsrc<float>(io.x_t, zw, g);
+            rz[2] = plane_rsrc<float>(io.x_t, wrap(p + 1, g.nz), g);
+            float rho[2];
+            pull_moments<WALLS>(rz, ppb, col, lk_a, rho, u_a);
+            r = make_float2(rho[0], rho[1]);
+          }
         }
         rring[(k % SL) * P2 + at2] = r;
       }
@@ -360,9 +374,13 @@ adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const Adjoint
           float2 r = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
           float uu[3] = {0.f, 0.f, 0.f};
           if (!(WALLS && (lk & 1u))) {
-            float rho[2];
-            pull_moments<WALLS>(rz, ppb, hcol[j], lk, rho, uu);
-            r = make_float2(rho[0], rho[1]);
+            if constexpr (FIELDS) {
+              read_fields(io.fields, static_cast<uint32_t>(zw) * g.nxy + hcol[j].cell, g.n, r, uu);
+            } else {
+              float rho[2];
+              pull_moments<WALLS>(rz, ppb, hcol[j], lk, rho, uu);
+              r = make_float2(rho[0], rho[1]);
+            }
           }
           rring[(k % SL) * P2 + hat2[j]] = r;
           if (j == 0) {
@@ -419,23 +437,28 @@ struct AdjTile {
 };
 constexpr AdjTile ADJ_TILES[ADJOINT_SHAPES] = {{64, 8, 3}, {32, 16, 2}, {32, 8, 2}, {64, 4, 3}};
 
-template <bool WALLS, bool REG, int BXT, int ROWS, int HW>
+template <bool WALLS, bool REG, bool FIELDS, int BXT, int ROWS, int HW>
 hipError_t launch_shape(const Grid& g, const Phys& ph, const Tiling& t, const AdjointIO& io, hipStream_t st) {
   using Sh = AdjShape<BXT, ROWS, HW>;
-  hipLaunchKernelGGL((adjoint_march_kernel<WALLS, REG, BXT, ROWS, HW>), dim3(t.blocks), dim3(Sh::NT), 0, st, g, ph,
-                     t, io);
+  hipLaunchKernelGGL((adjoint_march_kernel<WALLS, REG, FIELDS, BXT, ROWS, HW>), dim3(t.blocks), dim3(Sh::NT), 0, st,
+                     g, ph, t, io);
   return hipGetLastError();
+}
+
+template <bool WALLS, bool REG, bool FIELDS>
+hipError_t launch_shapes(const Grid& g, const Phys& ph, const Tiling& t, const AdjointIO& io, hipStream_t st) {
+  switch (t.tile) {
+    case 0: return launch_shape<WALLS, REG, FIELDS, 64, 8, 3>(g, ph, t, io, st);
+    case 1: return launch_shape<WALLS, REG, FIELDS, 32, 16, 2>(g, ph, t, io, st);
+    case 2: return launch_shape<WALLS, REG, FIELDS, 32, 8, 2>(g, ph, t, io, st);
+    case 3: return launch_shape<WALLS, REG, FIELDS, 64, 4, 3>(g, ph, t, io, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <bool WALLS, bool REG>
 hipError_t launch_variant(const Grid& g, const Phys& ph, const Tiling& t, const AdjointIO& io, hipStream_t st) {
-  switch (t.tile) {
-    case 0: return launch_shape<WALLS, REG, 64, 8, 3>(g, ph, t, io, st);
-    case 1: return launch_shape<WALLS, REG, 32, 16, 2>(g, ph, t, io, st);
-    case 2: return launch_shape<WALLS, REG, 32, 8, 2>(g, ph, t, io, st);
-    case 3: return launch_shape<WALLS, REG, 64, 4, 3>(g, ph, t, io, st);
-    default: return hipErrorInvalidValue;
-  }
+  return io.fields ? launch_shapes<WALLS, REG, true>(g, ph, t, io, st) : launch_shapes<WALLS, REG, false>(g, ph, t, io, st);
 }
 
 }  // namespace

@@ -299,6 +299,23 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
   return LBM_OK;
 }
 
+lbm_status lbm_step_fields(lbm_ctx* c, float* fields) {
+  if (!c || !fields) return LBM_EINVAL;
+  if (static_cast<void*>(fields) == c->buf[0] || static_cast<void*>(fields) == c->buf[1]) return LBM_EINVAL;
+  if (c->storage != Storage::F32 || c->ph.regularized == 2) return LBM_ENOTSUP;
+  const Tiling t = step_tiling(c);
+  if (t.blocks <= 0) return LBM_ENOTSUP;
+  MarchIO io;
+  io.src = c->buf[c->t & 1];
+  io.dst = c->buf[(c->t + 1) & 1];
+  io.links = c->links;
+  io.fields = fields;
+  const hipError_t e = launch_march(c->storage, Mode::StepFields, c->g, c->ph, t, io, c->stream);
+  if (e != hipSuccess) return LBM_EHIP;
+  ++c->t;
+  return LBM_OK;
+}
+
 // The diagnostics march (shape 64 x 8) and its fixed-order reduction, with
 // the per-workgroup partial sums in `partials` (t.blocks * 16 doubles).
 static lbm_status moments_launch(lbm_ctx* c, const Tiling& t, double* partials, float* rho, float* u_f,
@@ -403,11 +420,13 @@ size_t lbm_adjoint_work_bytes(const lbm_ctx* c) {
   return adjoint_work(adjoint_tiling(c));
 }
 
-lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, float* lam_out, void* work,
-                            size_t work_bytes, double* dparams, double* drho0) {
+static lbm_status adjoint_step(lbm_ctx* c, const void* x_t, const float* fields, const float* lam_in,
+                               float* lam_out, void* work, size_t work_bytes, double* dparams, double* drho0) {
   if (!c || !x_t || !lam_in || !lam_out || !work || !dparams) return LBM_EINVAL;
   if (work_bytes < lbm_adjoint_work_bytes(c)) return LBM_EINVAL;
   if (lam_in == lam_out || static_cast<const void*>(lam_in) == x_t || static_cast<const void*>(lam_out) == x_t)
+    return LBM_EINVAL;
+  if (fields && (static_cast<const void*>(fields) == x_t || fields == lam_in || fields == lam_out))
     return LBM_EINVAL;
   if (c->storage != Storage::F32 || c->ph.regularized == 2) return LBM_ENOTSUP;
   const Tiling t = adjoint_tiling(c);
@@ -419,9 +438,21 @@ lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, fl
   io.lam_out = lam_out;
   io.partials = static_cast<double*>(work);
   io.drho0 = drho0;
+  io.fields = fields;
   hipError_t e = launch_adjoint_march(c->g, c->ph, t, io, c->stream);
   if (e == hipSuccess) e = launch_finalize(io.partials, t.blocks, 3, -1, dparams, true, c->stream);
   return from_hip(e);
+}
+
+lbm_status lbm_adjoint_step(lbm_ctx* c, const void* x_t, const float* lam_in, float* lam_out, void* work,
+                            size_t work_bytes, double* dparams, double* drho0) {
+  return adjoint_step(c, x_t, nullptr, lam_in, lam_out, work, work_bytes, dparams, drho0);
+}
+
+lbm_status lbm_adjoint_step_fields(lbm_ctx* c, const void* x_t, const float* fields, const float* lam_in,
+                                   float* lam_out, void* work, size_t work_bytes, double* dparams, double* drho0) {
+  if (!fields) return LBM_EINVAL;
+  return adjoint_step(c, x_t, fields, lam_in, lam_out, work, work_bytes, dparams, drho0);
 }
 
 lbm_status lbm_adjoint_seed(lbm_ctx* c, const float* grad_rho, float* lam) {

@@ -108,7 +108,10 @@ struct Region {
   float p_g;  // symmetric coupling used in the pressure
 };
 
-enum class Mode : int { Step = 0, Moments = 1 };
+// Step: one step.  Moments: diagnostics.  StepFields: one step that also
+// writes, for every cell, rho^A, rho^B and u of the pull it collides (the
+// forward quantities the reverse step needs at that time level; FP32).
+enum class Mode : int { Step = 0, Moments = 1, StepFields = 2 };
 
 struct MarchIO {
   const void* src = nullptr;       // stored state X_t
@@ -118,6 +121,7 @@ struct MarchIO {
   float* uf_out = nullptr;         // Moments
   double* partials = nullptr;      // Moments: 16 per block
   Region region{};
+  float* fields = nullptr;         // StepFields: 5 N floats, rho^A, rho^B, u_x, u_y, u_z (cell order)
 };
 
 // One reverse step (adjoint_march.hip): lam_t = dL/dX_t from lam_{t+1} =
@@ -129,6 +133,7 @@ struct AdjointIO {
   float* lam_out = nullptr;         // lam_t (state layout)
   double* partials = nullptr;       // 3 per block: dL/dG (tied), dL/dtau_A, dL/dtau_B
   double* drho0 = nullptr;          // 2 N, sum_i w_i dL/df_i^a, or null
+  const float* fields = nullptr;    // rho^A, rho^B, u of X_t's pull (StepFields), or null: pull them
 };
 
 // Tile shapes of the reverse march: 0 = 64x8, 1 = 32x16, 2 = 32x8, 3 = 64x4

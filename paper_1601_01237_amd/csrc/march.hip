@@ -147,6 +147,18 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
       } else {
         ring[slot * PLANE + at] = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
       }
+      if constexpr (M == Mode::StepFields) {
+        // the chunk's own planes: rho~ (rho_s on wall cells) and u (0 there)
+        if (owner && k >= 1 && k < kmax) {
+          const uint32_t c = static_cast<uint32_t>(zw) * g.nxy + col_off;
+          const float2 rr = ring[slot * PLANE + at];
+          io.fields[c] = rr.x;
+          io.fields[n + c] = rr.y;
+          io.fields[2 * n + c] = solid ? 0.0f : nxt_u[0];
+          io.fields[3 * n + c] = solid ? 0.0f : nxt_u[1];
+          io.fields[4 * n + c] = solid ? 0.0f : nxt_u[2];
+        }
+      }
 
       if (k >= 1) {
         __syncthreads();
@@ -157,7 +169,7 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
           const bool csolid = WALLS && (cur_links & 1u);
           const uint32_t cell = static_cast<uint32_t>(zc) * g.nxy + col_off;
           if (owner) {
-            if constexpr (M == Mode::Step) {
+            if constexpr (M == Mode::Step || M == Mode::StepFields) {
               if (!csolid) {
                 shan_chen_finish<EX, 2>(ring + slot * PLANE, at, cur_S);
                 Local L;
@@ -431,9 +443,8 @@ static hipError_t launch_shape(const Grid& g, const Phys& ph, const Tiling& t, c
   return hipGetLastError();
 }
 
-template <Storage S, bool WALLS, int REG>
+template <Storage S, bool WALLS, int REG, Mode M = Mode::Step>
 static hipError_t launch_step(const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io, hipStream_t st) {
-  constexpr Mode M = Mode::Step;
   switch (t.tile) {
     case 0: return launch_shape<S, WALLS, M, 64, 8, 3, REG>(g, ph, t, io, st);
     case 1: return launch_shape<S, WALLS, M, 64, 12, 3, REG>(g, ph, t, io, st);
@@ -459,6 +470,14 @@ static hipError_t launch_tile(const Grid& g, const Phys& ph, const Tiling& t, co
     // Diagnostics use one shape (tile 0).
     if (t.tile != 0) return hipErrorInvalidValue;
     return launch_shape<S, WALLS, M, 64, 8, 3>(g, ph, t, io, st);
+  } else if constexpr (M == Mode::StepFields && S == Storage::F32) {
+    // the operators the reverse step has
+    if (!io.fields) return hipErrorInvalidValue;
+    switch (ph.regularized) {
+      case 0: return launch_step<S, WALLS, 0, M>(g, ph, t, io, st);
+      case 1: return launch_step<S, WALLS, 1, M>(g, ph, t, io, st);
+      default: return hipErrorInvalidValue;
+    }
   } else {
     return hipErrorInvalidValue;
   }
@@ -476,6 +495,7 @@ static hipError_t launch_mode(Mode mode, const Grid& g, const Phys& ph, const Ti
   switch (mode) {
     case Mode::Step: return launch_walls<S, Mode::Step>(g, ph, t, io, st);
     case Mode::Moments: return launch_walls<S, Mode::Moments>(g, ph, t, io, st);
+    case Mode::StepFields: return launch_walls<S, Mode::StepFields>(g, ph, t, io, st);
     default: return hipErrorInvalidValue;
   }
 }

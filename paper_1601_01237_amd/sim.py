@@ -154,6 +154,17 @@ class Sim:
     def step(self, n=1):
         _lib.check("lbm_step", self.lib.lbm_step(self.ctx, int(n)))
 
+    def step_fields(self, fields=None):
+        """One step that also writes rho~^A, rho~^B, u_x, u_y, u_z of the pull
+        it collides into ``fields`` (float32, 5 N, on the device; allocated
+        when None) and returns it: what the reverse step at this time level
+        reads instead of pulling the state again (lbm_step_fields)."""
+        import torch
+        if fields is None:
+            fields = torch.empty(5 * self.n, dtype=torch.float32, device=self.device)
+        _lib.check("lbm_step_fields", self.lib.lbm_step_fields(self.ctx, _ptr(fields)))
+        return fields
+
     def run(self, n, check_every=0):
         """Advance n steps.  With check_every > 0, read the diagnostics every
         check_every steps and after the last one, and raise LBMError with

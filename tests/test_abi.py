@@ -58,6 +58,8 @@ def test_null_arguments_are_rejected_without_a_gpu(lib):
     # null buffers -> invalid argument, checked before any HIP call
     assert lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), None, None, None, None, None) == -1
     assert lib.lbm_step(None, 1) == -1
+    assert lib.lbm_step_fields(None, None) == -1
+    assert lib.lbm_adjoint_step_fields(None, None, None, None, None, None, 0, None, None) == -1
     assert lib.lbm_moments(None, None, None, None, None) == -1
     assert lib.lbm_destroy(None) == 0
     assert lib.lbm_time(None) == -1

@@ -367,3 +367,78 @@ def test_adjoint_tiling_invariance(lib, collision, walls):
         assert torch.equal(lam, outs[0][0]) and torch.equal(drho, outs[0][1])
     for p in params[1:]:
         np.testing.assert_allclose(p, params[0], rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("collision", ["bgk", "regularized"])
+@pytest.mark.parametrize("walls", [False, True])
+def test_step_fields_and_reverse_with_fields(lib, walls, collision):
+    """lbm_step_fields advances the state exactly as lbm_step and writes the
+    densities and mixture velocity of the pull it collides (against the
+    oracle's Eqs. 4-6; rho_s and 0 on wall cells); the reverse step that
+    reads them is bitwise the reverse step that pulls them itself, for every
+    reverse-march shape."""
+    from paper_1601_01237_amd.autograd import Reverse, to_adjoint_layout
+    from paper_1601_01237_amd.sim import Sim
+    say(f"step fields and reverse with fields walls={walls} {collision}")
+    shape = (11, 21, 70)
+    solid = None
+    if walls:
+        solid = np.zeros(shape, bool)
+        solid[0] = True
+        solid[5, 3:9, 20:41] = True
+    f, rho = _random_state(shape, 31, solid)
+    if solid is not None:
+        rho[:, solid] = 0.0
+    p = olbm.Params(tau=(0.8, 1.2), G=((0.0, -1.3), (-0.7, 0.0)), rho_wall=(0.2, 0.1), collision=collision)
+    sim = Sim(rho, tau=p.tau, G=p.G, rho_wall=p.rho_wall, solid=solid, collision=collision)
+    sim.set_populations(torch.from_numpy(f.astype(np.float32)))
+    x_t = sim.state.clone()
+    ck = sim.checkpoint()
+    sim.step(1)
+    plain = sim.state.clone()
+    sim.restore(ck)
+    fields = sim.step_fields()
+    assert torch.equal(sim.state, plain) and sim.t == ck[1] + 1
+    # the fields against the oracle's moments of the same pre-collision f
+    fl = fields.view(5, *shape).cpu().numpy().astype(np.float64)
+    m = olbm.macroscopic(f, p, solid)
+    fluid = olbm.fluid_mask(shape, solid)
+    for a in range(2):
+        assert np.max(np.abs(fl[a] - m["rho_s"][a])[fluid]) <= 1e-5 * np.max(m["rho_s"][a])
+    assert np.max(np.abs(fl[2:] - m["u"])[:, fluid]) <= 1e-5 * max(1.0, np.max(np.abs(m["u"])))
+    if solid is not None:
+        assert np.all(fl[0][solid] == np.float32(0.2)) and np.all(fl[1][solid] == np.float32(0.1))
+        assert np.all(fl[2:][:, solid] == 0.0)
+    # reverse step with and without the fields
+    lam1 = np.random.default_rng(32).normal(size=f.shape).astype(np.float32)
+    if solid is not None:
+        lam1[:, :, solid] = 0.0
+    lam_in = to_adjoint_layout(torch.from_numpy(lam1).cuda(), sim)
+    live = sim.live_mask(sim.lam_layout)
+    for shp in (-1, 0, 1, 2, 3):
+        sim.set_adjoint_tiling(shp, 0)
+        r0, r1 = Reverse(sim), Reverse(sim)
+        a, da = r0.step(x_t, lam_in, want_drho0=True)
+        b, db = r1.step(x_t, lam_in, want_drho0=True, fields=fields)
+        torch.cuda.synchronize()
+        assert torch.equal(a[live], b[live]) and torch.equal(da, db), shp
+        np.testing.assert_allclose(r1.dparams.cpu().numpy(), r0.dparams.cpu().numpy(), rtol=1e-12, atol=0)
+    sim.close()
+
+
+def test_step_fields_refusals(lib):
+    """16-bit storage and the third-order reading have no reverse step, so no
+    fields step; null or aliased buffers are refused."""
+    import ctypes
+    from paper_1601_01237_amd.sim import Sim
+    rho0 = inputs.sphere_droplet((8, 8, 8), radius=2.0, seed=1)
+    buf = torch.empty(5 * 512, dtype=torch.float32, device="cuda")
+    for kw in (dict(storage="fp16"), dict(collision="regularized3")):
+        s = Sim(rho0, **kw)
+        assert s.lib.lbm_step_fields(s.ctx, ctypes.c_void_p(buf.data_ptr())) == -5
+        s.close()
+    s = Sim(rho0)
+    assert s.lib.lbm_step_fields(s.ctx, None) == -1
+    assert s.lib.lbm_step_fields(s.ctx, ctypes.c_void_p(s.state.data_ptr())) == -1
+    assert s.t == 0
+    s.close()
