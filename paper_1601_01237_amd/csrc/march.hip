@@ -149,14 +149,16 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
       }
       if constexpr (M == Mode::StepFields) {
         // the chunk's own planes: rho~ (rho_s on wall cells) and u (0 there)
+        // (non-temporal: read back by a reverse step much later, they should
+        // not displace the lines neighbouring tiles still need)
         if (owner && k >= 1 && k < kmax) {
           const uint32_t c = static_cast<uint32_t>(zw) * g.nxy + col_off;
           const float2 rr = ring[slot * PLANE + at];
-          io.fields[c] = rr.x;
-          io.fields[n + c] = rr.y;
-          io.fields[2 * n + c] = solid ? 0.0f : nxt_u[0];
-          io.fields[3 * n + c] = solid ? 0.0f : nxt_u[1];
-          io.fields[4 * n + c] = solid ? 0.0f : nxt_u[2];
+          __builtin_nontemporal_store(rr.x, io.fields + c);
+          __builtin_nontemporal_store(rr.y, io.fields + n + c);
+          __builtin_nontemporal_store(solid ? 0.0f : nxt_u[0], io.fields + 2 * n + c);
+          __builtin_nontemporal_store(solid ? 0.0f : nxt_u[1], io.fields + 3 * n + c);
+          __builtin_nontemporal_store(solid ? 0.0f : nxt_u[2], io.fields + 4 * n + c);
         }
       }
 

@@ -160,8 +160,16 @@ def cmd_run_adjoint(args):
     rev = Reverse(sim)
     lam = rev.seed(torch.ones((2, n, n, n), dtype=torch.float32, device=sim.device))
     x_t = sim.state.clone()
+    fields = None
+    if args.fields:
+        # the reverse sweep's path: the recomputed forward step writes the
+        # densities and velocity the reverse step reads
+        fields = torch.empty(5 * n ** 3, dtype=torch.float32, device=sim.device)
+        for _ in range(args.steps):
+            sim.restore((x_t, sim.t))
+            sim.step_fields(fields)
     for _ in range(args.steps):
-        lam, _ = rev.step(x_t, lam)
+        lam, _ = rev.step(x_t, lam, fields=fields)
     torch.cuda.synchronize()
     sim.close()
     print(f"[profiling] adjoint {n}^3: {args.steps} forward and {args.steps} reverse steps", flush=True)
@@ -186,6 +194,11 @@ def _is_copy(name):
 def _is_step(name):
     # single-cell march in Step mode, or the paired march (Step only)
     return ("march_kernel" in name and "(lbm::Mode)0" in name) or "march_pair_kernel" in name
+
+
+def _is_step_fields(name):
+    # the step that also writes the forward fields of the reverse step
+    return "march_kernel" in name and "(lbm::Mode)2" in name
 
 
 def _is_adjoint(name):
@@ -275,6 +288,8 @@ def _kernel_class(name):
         return "lbm_march_copy"
     if _is_step(name):
         return "step"
+    if _is_step_fields(name):
+        return "step+fields"
     return None
 
 
@@ -321,7 +336,8 @@ def cmd_counters(args):
                 key = (r["Counter_Name"], cls)
                 table.setdefault(key, []).append(float(r["Counter_Value"]))
     counters = sorted({k[0] for k in table})
-    classes = [c for c in ("lbm_stream_copy", "lbm_march_copy", "step", "reverse") if any(k[1] == c for k in table)]
+    classes = [c for c in ("lbm_stream_copy", "lbm_march_copy", "step", "step+fields", "reverse")
+               if any(k[1] == c for k in table)]
     lines = [args.title, "", f"command: {args.command}", "",
              f"{'counter (mean per dispatch)':32} " + " ".join(f"{c:>18}" for c in classes)]
     for name in counters:
@@ -386,6 +402,7 @@ def main(argv=None):
     ra.add_argument("--collision", default="bgk", choices=["bgk", "regularized"])
     ra.add_argument("--shape", type=int, default=-1, help="reverse-march tile shape (-1 = automatic)")
     ra.add_argument("--zchunk", type=int, default=0)
+    ra.add_argument("--fields", action="store_true", help="reverse steps read the forward fields (lbm_step_fields)")
     ra.add_argument("--copy-gib", type=float, default=2.0)
     ra.add_argument("--copy-reps", type=int, default=3)
     t = sub.add_parser("traffic")
