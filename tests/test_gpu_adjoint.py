@@ -85,7 +85,7 @@ def test_one_adjoint_step_matches_oracle(lib, walls, collision):
 @pytest.mark.parametrize("shape", [(3, 5, 9), (2, 3, 130), (5, 1, 4), (9, 13, 65)])
 def test_adjoint_step_ragged_grids(lib, shape, collision):
     """Grids thinner than one chunk (nz < 4), a single row, and x-y planes
-    that leave partial tiles in the march, gather and stream passes."""
+    that leave partial tiles in the reverse march."""
     from paper_1601_01237_amd.autograd import Reverse, from_adjoint_layout, to_adjoint_layout
     from paper_1601_01237_amd.sim import Sim
     say(f"adjoint ragged {shape} {collision}")
