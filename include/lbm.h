@@ -199,7 +199,9 @@ int64_t lbm_state_elems(int32_t nx, int32_t ny, int32_t nz, int32_t storage);
  *          pre-collision state is f_i^a = w_i rho0^a (Eq. 3 at u = 0) on fluid
  *          cells; solid cells carry no populations.
  *   stream hipStream_t as void*.
- * On success *ctx owns a host struct and (walls only) a device link mask.
+ * On success *ctx owns a host struct and (walls only) a device link mask:
+ * the 4-byte link words and, when there are few distinct words, the class
+ * bytes (lbm_wall_classes), 5 bytes per cell and 1 KiB.
  * Allocation failures return LBM_EHIP and leave *ctx NULL. */
 lbm_status lbm_init(lbm_ctx **ctx, const lbm_params *p, void *buf_a, void *buf_b,
                     const uint8_t *solid, const double *rho0, void *stream);
@@ -303,6 +305,17 @@ lbm_status lbm_set_tiling(lbm_ctx *ctx, int32_t tile, int32_t zchunk);
  *     it.
  * LBM_EINVAL for order outside 0..4 or x_offset outside -1..nx-1. */
 lbm_status lbm_set_placement(lbm_ctx *ctx, int32_t order, int32_t x_offset);
+
+/* Wall classes of a context with walls.  Bit i of a fluid cell's link word
+ * says whether x - c_i is a wall cell (the bounce-back of Eq. 1's
+ * streaming).  When the geometry's fluid cells show at most 256 distinct
+ * words, lbm_init also stores one class byte per cell, the index of its word
+ * in a table of those words, and the step, diagnostics and reverse marches
+ * read that byte instead of the 4-byte word.  Returns the number of classes
+ * in use (at least 2: the fluid cells away from walls, and the wall cells),
+ * 0 when the context has no walls or its geometry has more distinct words
+ * (the marches then read the words), -1 for a NULL context.  Host call. */
+int32_t lbm_wall_classes(const lbm_ctx *ctx);
 
 /* ---- Adjoint (reverse mode) of one step, FP32 storage -------------------
  * (16-bit storage forms and LBM_REGULARIZED3: LBM_ENOTSUP).  BGK (Eq. 2)

@@ -70,6 +70,7 @@ def _declare(lib):
         "lbm_set_time": (i32, [vp, i64]),
         "lbm_set_tiling": (i32, [vp, i32, i32]),
         "lbm_set_placement": (i32, [vp, i32, i32]),
+        "lbm_wall_classes": (i32, [vp]),
         "lbm_adjoint_work_bytes": (C.c_size_t, [vp]),
         "lbm_set_adjoint_tiling": (i32, [vp, i32, i32]),
         "lbm_adjoint_step": (i32, [vp, vp, vp, vp, vp, C.c_size_t, vp, vp]),
@@ -107,7 +108,7 @@ def check(func, code):
 EXPORTED = ["lbm_version", "lbm_velocity_set", "lbm_status_str", "lbm_plane_stride", "lbm_row_block",
             "lbm_state_elems", "lbm_row_half", "lbm_init", "lbm_step",
             "lbm_moments", "lbm_moments_static", "lbm_get_populations", "lbm_set_populations", "lbm_time",
-            "lbm_set_time", "lbm_set_tiling", "lbm_set_placement", "lbm_adjoint_work_bytes",
+            "lbm_set_time", "lbm_set_tiling", "lbm_set_placement", "lbm_wall_classes", "lbm_adjoint_work_bytes",
             "lbm_set_adjoint_tiling", "lbm_adjoint_step", "lbm_adjoint_step_fields", "lbm_step_fields",
             "lbm_adjoint_seed", "lbm_stream_copy", "lbm_march_copy", "lbm_destroy"]
 

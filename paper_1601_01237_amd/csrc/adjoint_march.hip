@@ -129,6 +129,9 @@ adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const Adjoint
   __shared__ float stash[STASH ? 2 * 2 * Q * Sh::NOWN : 1];
 
   const int tid = threadIdx.x;
+  // Link words of the wall classes (buffer.h).
+  __shared__ uint32_t ltab[WALLS ? WALL_CLASSES : 1];
+  if constexpr (WALLS) load_wall_classes(io.cls, io.ltab, ltab, tid, Sh::NT);
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   // Block order of the tiling (launch.h): with walls every chunk of a run of
   // tiles per XCD (the work of a chunk depends on the geometry).
@@ -170,7 +173,7 @@ adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const Adjoint
       if (k <= zc + 3) {
         const int p = z0 - 2 + k;
         const int zw = wrap(p, g.nz);
-        lk_a = WALLS ? io.links[static_cast<uint32_t>(zw) * g.nxy + col.cell] : 0u;
+        lk_a = WALLS ? cell_links(io.cls, ltab, io.links, static_cast<uint32_t>(zw) * g.nxy + col.cell) : 0u;
         float2 r = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
         if (!(WALLS && (lk_a & 1u))) {
           if constexpr (FIELDS) {
@@ -398,7 +401,7 @@ adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const Adjoint
 #pragma unroll
         for (int j = 0; j < Sh::HPL; ++j) {
           if (!has[j]) continue;
-          const uint32_t lk = WALLS ? io.links[static_cast<uint32_t>(zw) * g.nxy + hcol[j].cell] : 0u;
+          const uint32_t lk = WALLS ? cell_links(io.cls, ltab, io.links, static_cast<uint32_t>(zw) * g.nxy + hcol[j].cell) : 0u;
           float2 r = make_float2(ph.rho_wall[0], ph.rho_wall[1]);
           float uu[3] = {0.f, 0.f, 0.f};
           if (!(WALLS && (lk & 1u))) {

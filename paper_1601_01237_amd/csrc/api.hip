@@ -7,6 +7,8 @@
 #include <cstdlib>
 #include <mutex>
 #include <new>
+#include <unordered_map>
+#include <vector>
 
 #include "lbm.h"
 #include "launch.h"
@@ -20,6 +22,9 @@ struct lbm_ctx {
   Storage storage;
   void* buf[2];
   uint32_t* links;     // owned; null without walls
+  const uint8_t* cls;  // wall classes (in the links allocation), or null
+  const uint32_t* ltab;  // link word of each class (in the links allocation)
+  int classes;         // classes in use (0: none)
   hipStream_t stream;
   int64_t t;
   int tile, zchunk;    // tiling of the step kernel
@@ -199,6 +204,54 @@ int64_t lbm_state_elems(int32_t nx, int32_t ny, int32_t nz, int32_t storage) {
   return static_cast<int64_t>(nz) * static_cast<int64_t>(L.zstride);
 }
 
+// Wall classes of the link words (buffer.h): each cell's word (1 for a wall
+// cell) replaced by its index in a table of the distinct words, when there
+// are at most WALL_CLASSES of them.  Otherwise, or when the host cannot hold
+// the N words, the context keeps no classes and the marches read the words.
+static hipError_t build_wall_classes(lbm_ctx* c) {
+  const uint64_t n = c->g.n;
+  std::vector<uint32_t> words;
+  std::vector<uint8_t> cls;
+  try {
+    words.resize(n);
+    cls.resize(n);
+  } catch (const std::bad_alloc&) {
+    return hipSuccess;
+  }
+  hipError_t e = hipMemcpyAsync(words.data(), c->links, n * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  uint32_t table[WALL_CLASSES] = {0u, 1u};
+  int classes = 2;
+  std::unordered_map<uint32_t, int> index;
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint32_t w = (words[i] & 1u) ? 1u : words[i];
+    int k = static_cast<int>(w);  // 0: fluid away from walls, 1: wall cell
+    if (w > 1u) {
+      const auto it = index.find(w);
+      if (it != index.end()) {
+        k = it->second;
+      } else {
+        if (classes == WALL_CLASSES) return hipSuccess;
+        k = classes++;
+        table[k] = w;
+        index.emplace(w, k);
+      }
+    }
+    cls[i] = static_cast<uint8_t>(k);
+  }
+  uint32_t* tab = c->links + n;
+  uint8_t* dcls = reinterpret_cast<uint8_t*>(tab + WALL_CLASSES);
+  e = hipMemcpyAsync(tab, table, sizeof(table), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dcls, cls.data(), n, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the host arrays end here
+  if (e != hipSuccess) return e;
+  c->ltab = tab;
+  c->cls = dcls;
+  c->classes = classes;
+  return hipSuccess;
+}
+
 lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b, const uint8_t* solid,
                     const double* rho0, void* stream) {
   if (!out) return LBM_EINVAL;
@@ -241,6 +294,9 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
   c->buf[0] = buf_a;
   c->buf[1] = buf_b;
   c->links = nullptr;
+  c->cls = nullptr;
+  c->ltab = nullptr;
+  c->classes = 0;
   c->stream = static_cast<hipStream_t>(stream);
   c->t = 0;
   c->tile = -1;
@@ -263,11 +319,14 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* buf_a, void* buf_b
 
   hipError_t e = hipSuccess;
   if (solid) {
-    if (hipMalloc(reinterpret_cast<void**>(&c->links), n * sizeof(uint32_t)) != hipSuccess) {
+    // link words of every cell, the class table, one class byte per cell
+    const size_t bytes = n * sizeof(uint32_t) + WALL_CLASSES * sizeof(uint32_t) + n;
+    if (hipMalloc(reinterpret_cast<void**>(&c->links), bytes) != hipSuccess) {
       delete c;
       return LBM_EHIP;
     }
     e = launch_links(c->g, solid, c->links, c->stream);
+    if (e == hipSuccess) e = build_wall_classes(c);
   }
   // Both buffers get the rest state, so wall cells (never written by a step)
   // hold the same defined values in either time level.
@@ -292,6 +351,8 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
     io.src = c->buf[c->t & 1];
     io.dst = c->buf[(c->t + 1) & 1];
     io.links = c->links;
+    io.cls = c->cls;
+    io.ltab = c->ltab;
     const hipError_t e = launch_march(c->storage, Mode::Step, c->g, c->ph, t, io, c->stream);
     if (e != hipSuccess) return LBM_EHIP;
     ++c->t;
@@ -309,6 +370,8 @@ lbm_status lbm_step_fields(lbm_ctx* c, float* fields) {
   io.src = c->buf[c->t & 1];
   io.dst = c->buf[(c->t + 1) & 1];
   io.links = c->links;
+  io.cls = c->cls;
+  io.ltab = c->ltab;
   io.fields = fields;
   const hipError_t e = launch_march(c->storage, Mode::StepFields, c->g, c->ph, t, io, c->stream);
   if (e != hipSuccess) return LBM_EHIP;
@@ -323,6 +386,8 @@ static lbm_status moments_launch(lbm_ctx* c, const Tiling& t, double* partials, 
   MarchIO io;
   io.src = c->buf[c->t & 1];
   io.links = c->links;
+  io.cls = c->cls;
+  io.ltab = c->ltab;
   io.rho_out = rho;
   io.uf_out = u_f;
   io.partials = partials;  // written even without diag
@@ -402,6 +467,8 @@ lbm_status lbm_set_placement(lbm_ctx* c, int32_t order, int32_t x_offset) {
   return LBM_OK;
 }
 
+int32_t lbm_wall_classes(const lbm_ctx* c) { return c ? c->classes : -1; }
+
 lbm_status lbm_set_adjoint_tiling(lbm_ctx* c, int32_t shape, int32_t zchunk) {
   if (!c || shape < -1 || shape >= ADJOINT_SHAPES || zchunk < 0) return LBM_EINVAL;
   c->adj_shape = shape;
@@ -434,6 +501,8 @@ static lbm_status adjoint_step(lbm_ctx* c, const void* x_t, const float* fields,
   AdjointIO io;
   io.x_t = x_t;
   io.links = c->links;
+  io.cls = c->cls;
+  io.ltab = c->ltab;
   io.lam_in = lam_in;
   io.lam_out = lam_out;
   io.partials = static_cast<double*>(work);

@@ -113,7 +113,38 @@ __device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_
 }
 
 // Wall links (one 32-bit word per cell): bit i set when x - c_i is a wall
-// cell, bit 0 when x itself is.
+// cell, bit 0 when x itself is.  When the geometry's fluid cells show at
+// most WALL_CLASSES distinct words, every cell also has a one-byte class,
+// the index of its word in a table of those words (a wall cell takes the
+// class of the word 1: the marches use only bit 0 of a wall cell).  The
+// marches then hold the table in LDS and read one byte of wall data per
+// cell; cls == nullptr means the geometry has no classes and they read the
+// words.
+
+// The wall data a march loads for cell c: its class byte, or its link word
+// when the geometry has no classes.
+__device__ __forceinline__ uint32_t wall_raw(const uint8_t* __restrict__ cls, const uint32_t* __restrict__ links,
+                                             uint32_t c) {
+  return cls ? static_cast<uint32_t>(cls[c]) : links[c];
+}
+// The link word of that data (ltab: the class table in LDS).
+__device__ __forceinline__ uint32_t link_word(const uint8_t* cls, const uint32_t* ltab, uint32_t raw) {
+  return cls ? ltab[raw] : raw;
+}
+__device__ __forceinline__ uint32_t cell_links(const uint8_t* __restrict__ cls, const uint32_t* ltab,
+                                               const uint32_t* __restrict__ links, uint32_t c) {
+  return link_word(cls, ltab, wall_raw(cls, links, c));
+}
+
+// Copies the class table into LDS (a workgroup barrier follows when there
+// is one; all threads of the workgroup call this).
+__device__ __forceinline__ void load_wall_classes(const uint8_t* cls, const uint32_t* __restrict__ table,
+                                                  uint32_t* ltab, int tid, int nthreads) {
+  if (!cls) return;
+  for (int i = tid; i < WALL_CLASSES; i += nthreads) ltab[i] = table[i];
+  __syncthreads();
+}
+
 __device__ __forceinline__ bool is_solid(const uint32_t* links, uint64_t c) { return links && (links[c] & 1u); }
 // Neighbour x + c_i is a wall: bit opp(i) of x.
 __device__ __forceinline__ bool ahead_solid(const uint32_t* links, uint64_t c, int i) {

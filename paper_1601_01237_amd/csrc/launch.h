@@ -113,10 +113,15 @@ struct Region {
 // forward quantities the reverse step needs at that time level; FP32).
 enum class Mode : int { Step = 0, Moments = 1, StepFields = 2 };
 
+// Entries of the wall class table (buffer.h).
+constexpr int WALL_CLASSES = 256;
+
 struct MarchIO {
   const void* src = nullptr;       // stored state X_t
   void* dst = nullptr;             // Step: X_{t+1}
   const uint32_t* links = nullptr; // wall link bits or null
+  const uint8_t* cls = nullptr;    // wall class per cell, or null (buffer.h)
+  const uint32_t* ltab = nullptr;  // link word of each class (WALL_CLASSES)
   float* rho_out = nullptr;        // Moments
   float* uf_out = nullptr;         // Moments
   double* partials = nullptr;      // Moments: 16 per block
@@ -129,6 +134,8 @@ struct MarchIO {
 struct AdjointIO {
   const void* x_t = nullptr;        // stored state X_t (FP32, state layout)
   const uint32_t* links = nullptr;  // wall link bits or null
+  const uint8_t* cls = nullptr;     // wall class per cell, or null (buffer.h)
+  const uint32_t* ltab = nullptr;   // link word of each class (WALL_CLASSES)
   const float* lam_in = nullptr;    // lam_{t+1} (state layout)
   float* lam_out = nullptr;         // lam_t (state layout)
   double* partials = nullptr;       // 3 per block: dL/dG (tied), dL/dtau_A, dL/dtau_B

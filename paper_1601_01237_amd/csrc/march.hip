@@ -82,6 +82,9 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
   __shared__ double red[(Sh::NT / 64) * 16];
 
   const int tid = threadIdx.x;
+  // Link words of the wall classes (buffer.h).
+  __shared__ uint32_t ltab[WALLS ? WALL_CLASSES : 1];
+  if constexpr (WALLS) load_wall_classes(io.cls, io.ltab, ltab, tid, Sh::NT);
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   // Which tile and z chunk: the launch's block order (launch.h).
   const TileCoord tc = tile_of_block(b, tl);
@@ -127,6 +130,10 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) cur_S[0][c] = cur_S[1][c] = nxt_S[0][c] = nxt_S[1][c] = 0.f;
     uint32_t cur_links = 0, nxt_links = 0;
+    // Wall data of the plane pulled next, loaded one plane ahead (the pull
+    // addresses of a plane depend on its link words).
+    uint32_t ahead = 0;
+    if constexpr (WALLS) ahead = wall_raw(io.cls, io.links, static_cast<uint32_t>(wrap(z0 - 1, g.nz)) * g.nxy + col_off);
     int slot = 0;  // k % 5
 
     for (int k = 0; k <= kmax; ++k) {
@@ -136,7 +143,10 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
       rz[0] = plane_rsrc<T>(io.src, wrap(p - 1, g.nz), g);
       rz[1] = plane_rsrc<T>(io.src, zw, g);
       rz[2] = plane_rsrc<T>(io.src, wrap(p + 1, g.nz), g);
-      if constexpr (WALLS) nxt_links = io.links[static_cast<uint32_t>(zw) * g.nxy + col_off];
+      if constexpr (WALLS) {
+        nxt_links = link_word(io.cls, ltab, ahead);
+        if (k < kmax) ahead = wall_raw(io.cls, io.links, static_cast<uint32_t>(wrap(p + 1, g.nz)) * g.nxy + col_off);
+      }
       const bool solid = WALLS && (nxt_links & 1u);
       if (!solid) {
         pull<S, WALLS>(rz, ppb, col, nxt_links, ws, nxt, nxt_d);
@@ -295,7 +305,7 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
       for (int j = 0; j < Sh::HPL; ++j) {
         if (!has[j]) continue;
         uint32_t lk = 0;
-        if constexpr (WALLS) lk = io.links[static_cast<uint32_t>(zw) * g.nxy + hcol_off[j]];
+        if constexpr (WALLS) lk = cell_links(io.cls, ltab, io.links, static_cast<uint32_t>(zw) * g.nxy + hcol_off[j]);
         float2 r;
         if (WALLS && (lk & 1u)) {
           r = make_float2(ph.rho_wall[0], ph.rho_wall[1]);

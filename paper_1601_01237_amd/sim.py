@@ -199,6 +199,11 @@ class Sim:
         1..4) and the x shift of the tile grid (-1 = automatic); see lbm_set_placement."""
         _lib.check("lbm_set_placement", self.lib.lbm_set_placement(self.ctx, int(order), int(x_offset)))
 
+    def wall_classes(self):
+        """Number of one-byte wall classes the marches read (0: they read the 4-byte link words;
+        see lbm_wall_classes)."""
+        return int(self.lib.lbm_wall_classes(self.ctx))
+
     def set_adjoint_tiling(self, shape=-1, zchunk=0):
         """Tile shape of the reverse march (-1 = automatic, 0..3, see
         lbm_set_adjoint_tiling) and z planes per workgroup (0 = default)."""

@@ -218,6 +218,7 @@ def test_size_limits_agree_with_init(lib, nx, ny, nz, storage, ok):
 def test_status_of_calls_on_a_null_context(lib):
     assert lib.lbm_set_tiling(None, -1, 0) == -1
     assert lib.lbm_set_placement(None, 0, -1) == -1
+    assert lib.lbm_wall_classes(None) == -1
     assert lib.lbm_moments(None, None, None, None, None) == -1
     assert lib.lbm_adjoint_seed(None, None, None) == -1
     assert lib.lbm_destroy(None) == 0

@@ -31,22 +31,29 @@ def _random_state(shape, seed, solid=None):
 
 
 @pytest.mark.parametrize("collision", ["bgk", "regularized"])
-@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("walls", [None, "obstacle", "porous"])
 def test_one_adjoint_step_matches_oracle(lib, walls, collision):
+    """The obstacle geometry takes the one-byte wall classes, the random
+    porous one (more distinct link words than classes) the link words."""
     from paper_1601_01237_amd.autograd import Reverse, from_adjoint_layout, to_adjoint_layout
     from paper_1601_01237_amd.sim import Sim
     say(f"adjoint one step walls={walls} {collision}")
     shape = (7, 9, 70)
     solid = None
-    if walls:
+    if walls == "obstacle":
         solid = np.zeros(shape, bool)
         solid[0] = True
         solid[3, 2:6, 10:30] = True
+    elif walls == "porous":
+        solid = np.random.default_rng(23).uniform(size=shape) < 0.3
+        solid[0] = True
     f, rho = _random_state(shape, 1, solid)
     p = olbm.Params(tau=(0.8, 1.3), G=((0.0, -1.4), (-0.6, 0.0)), rho_wall=(0.15, 0.35), collision=collision)
     if solid is not None:
         rho[:, solid] = 0.0
     sim = Sim(rho, tau=p.tau, G=p.G, rho_wall=p.rho_wall, solid=solid, collision=collision)
+    if walls:
+        assert (sim.wall_classes() > 0) == (walls == "obstacle")
     sim.set_populations(torch.from_numpy(f.astype(np.float32)))
     lam1 = np.random.default_rng(2).normal(size=f.shape)
     if solid is not None:

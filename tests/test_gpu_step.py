@@ -104,6 +104,7 @@ def test_walls_inclined_channel(lib):
     rho0, solid = inputs.inclined_channel(shape, angle_deg=30.0, radius=4.0, seed=3)
     p = olbm.Params(tau=(0.7, 0.7), G=((0.0, -1.0), (-1.0, 0.0)), rho_wall=(0.05, 0.2))
     sim = _sim(rho0, p, solid=solid)
+    assert sim.wall_classes() > 2  # the marches read one-byte wall classes
     sim.step(6)
     f_ref = oracle_run(rho0, p, 6, solid)
     compare_fields(sim, f_ref, p, solid=solid, tol=TOL, label="walls")
@@ -129,6 +130,43 @@ def test_walls_ragged_with_obstacle(lib):
     sim.step(5)
     f_ref = oracle_run(rho0, p, 5, solid)
     compare_fields(sim, f_ref, p, solid=solid, tol=TOL, label="walls ragged")
+    sim.close()
+
+
+def _wall_classes_expected(solid):
+    """Classes the library should keep for a geometry: the fluid cells' link
+    words (bit i: x - c_i is a wall cell), their distinct nonzero values plus
+    the class of the fluid cells away from walls and that of the wall cells,
+    or 0 beyond 256.  The count does not depend on the order of the bits."""
+    words = np.zeros(solid.shape, np.int64)
+    for i in range(1, olbm.Q):
+        words |= olbm.at_offset(solid, -olbm.C[i]).astype(np.int64) << i
+    fluid_words = np.unique(words[~solid])
+    n = 2 + int(np.count_nonzero(fluid_words))
+    return n if n <= 256 else 0
+
+
+@pytest.mark.parametrize("fill,expect_classes", [(0.01, True), (0.3, False)])
+def test_walls_porous_classes_and_words(lib, fill, expect_classes):
+    """Random porous media: a sparse one keeps the one-byte wall classes
+    (173 of them: class bytes above 127 too), a dense one has too many
+    distinct link words and the marches read the words; both match the
+    oracle."""
+    say(f"walls porous fill={fill}")
+    shape = (18, 13, 70)
+    rng = np.random.default_rng(21)
+    solid = rng.uniform(size=shape) < fill
+    solid[0] = True
+    rho0 = 0.3 + rng.uniform(0.0, 0.7, size=(2,) + shape)
+    rho0[:, solid] = 0.0
+    p = olbm.Params(tau=(0.9, 1.1), G=((0.0, -1.2), (-1.2, 0.0)), rho_wall=(0.2, 0.3))
+    sim = _sim(rho0, p, solid=solid)
+    want = _wall_classes_expected(solid)
+    assert sim.wall_classes() == want
+    assert (want > 2) == expect_classes
+    sim.step(4)
+    f_ref = oracle_run(rho0, p, 4, solid)
+    compare_fields(sim, f_ref, p, solid=solid, tol=TOL, label=f"porous {fill}")
     sim.close()
 
 
