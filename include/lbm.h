@@ -203,7 +203,7 @@ int64_t lbm_state_elems(int32_t nx, int32_t ny, int32_t nz, int32_t storage);
  * the 4-byte link words and, when there are few distinct words, the class
  * bytes (lbm_wall_classes), 5 bytes per cell and 1 KiB.  With walls the
  * call waits for the stream: it reads the link words back to the host once
- * to number the classes (4 bytes per cell of pageable host memory, freed
+ * to number the classes (5 bytes per cell of pageable host memory, freed
  * before it returns).
  * Allocation failures return LBM_EHIP and leave *ctx NULL. */
 lbm_status lbm_init(lbm_ctx **ctx, const lbm_params *p, void *buf_a, void *buf_b,
