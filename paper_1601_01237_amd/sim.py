@@ -75,7 +75,10 @@ class Sim:
         fluid = np.ones(self.shape, bool) if solid is None else ~np.asarray(solid, bool)
         if rho_shift is None:
             r = rho0.numpy()
-            rho_shift = tuple(float(r[a][fluid].mean()) for a in range(2)) if storage != "fp32" else (0.0, 0.0)
+            if storage == "fp32" or not fluid.any():
+                rho_shift = (0.0, 0.0)
+            else:
+                rho_shift = tuple(float(r[a][fluid].mean()) for a in range(2))
         self.rho_shift = tuple(float(v) for v in rho_shift)
         self.G = coupling_matrix(G)
         self.tau = tuple(float(t) for t in (tau if not np.isscalar(tau) else (tau, tau)))

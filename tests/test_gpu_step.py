@@ -170,6 +170,32 @@ def test_walls_porous_classes_and_words(lib, fill, expect_classes):
     sim.close()
 
 
+@pytest.mark.parametrize("case", ["all_solid", "one_cell", "slab"])
+def test_walls_degenerate_geometries(lib, case):
+    """A grid with no fluid cell, one fluid cell enclosed by walls (it keeps
+    its populations by bounce-back and feels no net wall force), and a fluid
+    layer one cell thick between walls."""
+    say(f"walls degenerate {case}")
+    shape = (6, 9, 70)
+    rng = np.random.default_rng(31)
+    solid = np.ones(shape, bool)
+    if case == "one_cell":
+        solid[3, 4, 40] = False
+    elif case == "slab":
+        solid[3] = False
+    rho0 = np.where(solid, 0.0, 0.3 + rng.uniform(0.0, 0.7, size=(2,) + shape))
+    p = olbm.Params(tau=(0.8, 1.1), G=((0.0, -1.5), (-1.5, 0.0)), rho_wall=(0.2, 0.3))
+    sim = _sim(rho0, p, solid=solid)
+    assert sim.wall_classes() == _wall_classes_expected(solid) == (2 if case == "all_solid" else 3)
+    sim.step(5)
+    f_ref = oracle_run(rho0, p, 5, solid)
+    _, diag = compare_fields(sim, f_ref, p, solid=solid, tol=TOL, label=case)
+    assert diag["vector"][7] == np.count_nonzero(~solid)
+    if case == "one_cell":
+        np.testing.assert_allclose(sim.moments()[0].cpu().numpy()[:, 3, 4, 40], rho0[:, 3, 4, 40], rtol=1e-6)
+    sim.close()
+
+
 def _state_after(rho0, p, steps, tile, zchunk, solid=None, place=(0, -1)):
     sim = _sim(rho0, p, solid=solid)
     sim.set_tiling(tile, zchunk)
