@@ -100,6 +100,8 @@ def run_case(shape, storage, steps, warmup, rho0=None, solid=None, tau=1.0, G=-1
         # (restored afterwards), before the warmup
         tile, best, _ = sim.tune(tiles=TUNE_TILES)
         tuned = dict(tile=tile, zchunk=best)
+    if solid is not None:
+        tuned["wall_classes"] = sim.wall_classes()  # 0: the marches read 4-byte link words
     ms, per, mean_ms = time_steps(sim, steps, warmup)
     _, _, diag = sim.moments(want_fields=False)
     n = int(np.prod(shape))
