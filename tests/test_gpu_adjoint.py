@@ -262,14 +262,18 @@ def test_calibration_gradient_full_size_against_central_differences(lib, n, step
     assert abs(ad_r - fd_r) <= 1e-2 * abs(fd_r), (ad_r, fd_r)
 
 
+@pytest.mark.parametrize("fields", [False, True])
 @pytest.mark.parametrize("collision,tau", [("bgk", 1.0), ("regularized", 0.8)])
-def test_adjoint_step_96cube_all_cells(lib, collision, tau):
+def test_adjoint_step_96cube_all_cells(lib, collision, tau, fields):
     """One reverse step of the differentiation workload at its full size
     (96^3 droplet, R = 20, G = -1, automatic tiling as timed), every cell
-    against the oracle; tau = 1 with BGK, 0.8 with the regularized collision."""
+    against the oracle; tau = 1 with BGK, 0.8 with the regularized collision.
+    With ``fields`` the reverse step reads the densities and velocity a
+    forward step wrote (the path the benchmark times) and must equal the
+    pulling reverse step bitwise."""
     from paper_1601_01237_amd.autograd import Reverse, from_adjoint_layout, to_adjoint_layout
     from paper_1601_01237_amd.sim import Sim
-    say(f"adjoint one step 96^3 {collision}")
+    say(f"adjoint one step 96^3 {collision} fields={fields}")
     n = 96
     rho0 = inputs.sphere_droplet((n, n, n), radius=20.0, seed=0)
     p = olbm.Params(tau=(tau, tau), G=((0.0, -1.0), (-1.0, 0.0)), collision=collision)
@@ -278,9 +282,18 @@ def test_adjoint_step_96cube_all_cells(lib, collision, tau):
     f = sim.populations().cpu().numpy().astype(np.float64)   # pre-collision f at t = 20
     lam1 = np.random.default_rng(9).normal(size=f.shape).astype(np.float32)
     rev = Reverse(sim)
-    lam_gpu, drho = rev.step(sim.state, to_adjoint_layout(torch.from_numpy(lam1).cuda(), sim), want_drho0=True)
+    x_t = sim.state.clone()
+    lam_in = to_adjoint_layout(torch.from_numpy(lam1).cuda(), sim)
+    lam_gpu, drho = rev.step(x_t, lam_in, want_drho0=True)
     got = from_adjoint_layout(lam_gpu, sim).cpu().numpy()
     d = rev.dparams.cpu().numpy()
+    if fields:
+        fl = sim.step_fields()  # the forward step from x_t, with its fields
+        rev_f = Reverse(sim)
+        lam_f, drho_f = rev_f.step(x_t, lam_in, want_drho0=True, fields=fl)
+        live = sim.live_mask(sim.lam_layout)
+        assert torch.equal(lam_f[live], lam_gpu[live]) and torch.equal(drho_f, drho)
+        np.testing.assert_allclose(rev_f.dparams.cpu().numpy(), d, rtol=1e-12, atol=0)
     sim.close()
     mu, dG, dtau = oadj.collide_adjoint(f, lam1.astype(np.float64), p)
     want = oadj.stream_adjoint(mu)
