@@ -342,10 +342,12 @@ march_kernel(const Grid g, const Phys ph, const Tiling tl, const MarchIO io) {
 
 // Tile shapes selectable at run time: (columns of cells, rows, halo waves);
 // shapes 6..9 are the paired march over folded 16-bit rows (2 cells per lane).
+// 64 x 12 takes two halo waves (some lanes fill two ring cells): against
+// three, 3% faster on the inclined-channel walls case, the same on open boxes.
 struct TileShape {
   int bx, rows, hw;
 };
-constexpr TileShape TILES[] = {{64, 8, 3},  {64, 12, 3}, {32, 16, 2}, {128, 4, 3}, {64, 4, 3},
+constexpr TileShape TILES[] = {{64, 8, 3},  {64, 12, 2}, {32, 16, 2}, {128, 4, 3}, {64, 4, 3},
                                {256, 2, 3}, {128, 8, 3}, {64, 16, 2}, {64, 8, 2},  {64, 12, 2}};
 static_assert(sizeof(TILES) / sizeof(TILES[0]) == TILE_SHAPES, "one entry per tile shape");
 constexpr int NTILES = sizeof(TILES) / sizeof(TILES[0]);
@@ -459,7 +461,7 @@ template <Storage S, bool WALLS, int REG, Mode M = Mode::Step>
 static hipError_t launch_step(const Grid& g, const Phys& ph, const Tiling& t, const MarchIO& io, hipStream_t st) {
   switch (t.tile) {
     case 0: return launch_shape<S, WALLS, M, 64, 8, 3, REG>(g, ph, t, io, st);
-    case 1: return launch_shape<S, WALLS, M, 64, 12, 3, REG>(g, ph, t, io, st);
+    case 1: return launch_shape<S, WALLS, M, 64, 12, 2, REG>(g, ph, t, io, st);
     case 2: return launch_shape<S, WALLS, M, 32, 16, 2, REG>(g, ph, t, io, st);
     case 3: return launch_shape<S, WALLS, M, 128, 4, 3, REG>(g, ph, t, io, st);
     case 4: return launch_shape<S, WALLS, M, 64, 4, 3, REG>(g, ph, t, io, st);
