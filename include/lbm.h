@@ -343,7 +343,8 @@ size_t lbm_adjoint_work_bytes(const lbm_ctx *ctx);
 /* Tiling of the reverse march (results do not depend on it, up to the
  * summation order of dparams): shape 0 = 64x8, 1 = 32x16, 2 = 32x8, 3 = 64x4
  * cells, or -1 (the default) for the automatic choice -- 32x8 or 64x4,
- * whichever pads the x-y plane less; zchunk = z planes per workgroup, 0 =
+ * whichever pads the x-y plane less, 64x4 on a tie; zchunk = z planes per
+ * workgroup, 0 =
  * the default, which minimises (rounds of 256 workgroups) x (zchunk + 5).
  * lbm_adjoint_work_bytes follows this setting.  Host-side setting;
  * LBM_EINVAL outside these ranges. */

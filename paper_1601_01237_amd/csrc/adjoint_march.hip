@@ -547,11 +547,14 @@ Tiling adjoint_march_tiling(const Grid& g, int shape, int zchunk) {
 int adjoint_auto_shape(const Grid& g, bool walls, int collision) {
   // The 256-cell tiles (32 x 8 and 64 x 4: six and seven waves, about 220
   // registers without spills, and the LDS to keep lam for BGK) measured
-  // fastest at 96^3; the 512-cell tiles spill with walls or the regularized
-  // transpose.  The one that pads the x-y plane less (32 x 8 on a tie).
+  // fastest; the 512-cell tiles spill with walls or the regularized
+  // transpose.  The one that pads the x-y plane less, 64 x 4 on a tie: its
+  // rows are two 128-byte lines wide (BGK reverse step 4% faster at 128^3
+  // and 192^3, 16% at 256^3); at 96^3, where 64 x 4 pads x to 128, 32 x 8
+  // is 17% faster.
   (void)walls;
   (void)collision;
-  const int first = 2, second = 3;
+  const int first = 3, second = 2;
   int best = first;
   long long best_cells = -1;
   for (int k : {first, second}) {
