@@ -279,10 +279,11 @@ lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
  * folded 32-bit word (two cells) per lane, for 16-bit storage with folded
  * rows and no walls only (else LBM_EINVAL), in words by rows: 6 = 64x8,
  * 7 = 32x16, 8 = 32x8, 9 = 32x12.  -1 (the default) picks 8 for folded
- * 16-bit rows without walls, else among 128x4, 64x8 and 32x16 (64x8
- * and 32x16 with walls or 16-bit storage), the one that pads the x-y plane
- * least, the first listed on a tie; an FP32 context without walls whose
- * choice would launch at most 128 workgroups takes 64x4.  The default z chunk of a context
+ * 16-bit rows without walls; with walls or 16-bit storage, of 64x8 and
+ * 32x16 the one that pads the x-y plane least (64x8 on a tie); for FP32
+ * without walls the first of 128x4, 64x12, 64x8 and 32x16 whose padded x-y
+ * plane is at most 1.3 times the least padded one, and 64x4 when that
+ * choice would launch at most 128 workgroups.  The default z chunk of a context
  * without walls minimises (rounds of 256 workgroups) x (chunk + 2) over
  * chunks of 4 to 256 planes (512 for the folded shapes); with walls it is
  * about nz * tiles / 512 planes, 8 to 256.  Results do not depend on this

@@ -420,32 +420,37 @@ Tiling make_tiling(const Grid& g, int tile, int zchunk, bool open_box) {
 
 int auto_tile(const Grid& g, bool walls, int elem_bytes) {
   // FP32 without walls: widest rows first (128-lane rows read whole 512-byte
-  // population rows).  With walls (the 128 x 4 shape keeps too few registers
-  // for the wall path) and for unfolded 16-bit rows (measured faster) 64 x 8
-  // comes first.  Folded 16-bit rows without walls take the paired march in
-  // 32 x 8 words (measured fastest of the pair shapes at 512^3: one 128-byte
-  // line per population row and six waves per CU).
-  // A later shape wins only by padding the x-y plane less (lanes past nx or
-  // ny do no work).
-  static constexpr int open_order[] = {3, 0, 2};
+  // population rows), then 64 x 12; a shape is taken when it pads the x-y
+  // plane (lanes past nx or ny do no work) by at most 30% more than the least
+  // padded candidate, the first such in this order.  Measured (open cubes,
+  // ms per step, against the least padded shape alone): 144^3 0.239 (64 x 12)
+  // against 0.266, 192^3 0.444 (64 x 12) against 0.473, 224^3 0.749
+  // (128 x 4, padded 14%) against 0.871.  With walls (the 128 x 4 shape
+  // keeps too few registers for the wall path) and for unfolded 16-bit rows
+  // 64 x 8 comes first, and the least padded shape wins (64 x 12 was 14%
+  // faster on an inclined channel but 25% slower on a random porous medium).
+  // Folded 16-bit rows without walls take the paired march in 32 x 8 words
+  // (measured fastest of the pair shapes at 512^3: one 128-byte line per
+  // population row and six waves per CU).
+  static constexpr int open_order[] = {3, 1, 0, 2};
   static constexpr int tall_order[] = {0, 2};
   static constexpr int pair_order[] = {8};
   const bool paired = elem_bytes == 2 && g.half != 0 && !walls;
   const bool tall = walls || elem_bytes != 4;
   const int* order = paired ? pair_order : (tall ? tall_order : open_order);
-  const int count = paired ? 1 : (tall ? 2 : 3);
-  int best = order[0];
-  long long best_cells = -1;
+  const int count = paired ? 1 : (tall ? 2 : 4);
+  const long long slack = (paired || tall) ? 10 : 13;  // tenths of the least padded plane
+  long long cells[4];
+  long long least = -1;
   for (int k = 0; k < count; ++k) {
     const TileShape sh = TILES[order[k]];
-    const long long cells = static_cast<long long>((g.nx + sh.bx - 1) / sh.bx) * sh.bx *
-                            (static_cast<long long>((g.ny + sh.rows - 1) / sh.rows) * sh.rows);
-    if (best_cells < 0 || cells < best_cells) {
-      best_cells = cells;
-      best = order[k];
-    }
+    cells[k] = static_cast<long long>((g.nx + sh.bx - 1) / sh.bx) * sh.bx *
+               (static_cast<long long>((g.ny + sh.rows - 1) / sh.rows) * sh.rows);
+    if (least < 0 || cells[k] < least) least = cells[k];
   }
-  return best;
+  for (int k = 0; k < count; ++k)
+    if (cells[k] * 10 <= least * slack) return order[k];
+  return order[0];
 }
 
 template <Storage S, bool WALLS, Mode M, int BXT, int ROWS, int HW, int REG = 0>
