@@ -146,27 +146,28 @@ def _wall_classes_expected(solid):
     return n if n <= 256 else 0
 
 
+@pytest.mark.parametrize("collision", ["bgk", "regularized", "regularized3"])
 @pytest.mark.parametrize("fill,expect_classes", [(0.01, True), (0.3, False)])
-def test_walls_porous_classes_and_words(lib, fill, expect_classes):
+def test_walls_porous_classes_and_words(lib, fill, expect_classes, collision):
     """Random porous media: a sparse one keeps the one-byte wall classes
     (173 of them: class bytes above 127 too), a dense one has too many
     distinct link words and the marches read the words; both match the
-    oracle."""
-    say(f"walls porous fill={fill}")
+    oracle, with each collision operator."""
+    say(f"walls porous fill={fill} {collision}")
     shape = (18, 13, 70)
     rng = np.random.default_rng(21)
     solid = rng.uniform(size=shape) < fill
     solid[0] = True
     rho0 = 0.3 + rng.uniform(0.0, 0.7, size=(2,) + shape)
     rho0[:, solid] = 0.0
-    p = olbm.Params(tau=(0.9, 1.1), G=((0.0, -1.2), (-1.2, 0.0)), rho_wall=(0.2, 0.3))
-    sim = _sim(rho0, p, solid=solid)
+    p = olbm.Params(tau=(0.9, 1.1), G=((0.0, -1.2), (-1.2, 0.0)), rho_wall=(0.2, 0.3), collision=collision)
+    sim = _sim(rho0, p, solid=solid, collision=collision)
     want = _wall_classes_expected(solid)
     assert sim.wall_classes() == want
     assert (want > 2) == expect_classes
     sim.step(4)
     f_ref = oracle_run(rho0, p, 4, solid)
-    compare_fields(sim, f_ref, p, solid=solid, tol=TOL, label=f"porous {fill}")
+    compare_fields(sim, f_ref, p, solid=solid, tol=TOL, label=f"porous {fill} {collision}")
     sim.close()
 
 
