@@ -65,22 +65,31 @@ def test_pair_shapes_rejected_where_rows_are_not_folded(lib):
     sim.close()
 
 
-@pytest.mark.parametrize("shape,walls", [((12, 10, 15), False), ((10, 9, 22), False), ((10, 9, 22), True)])
+@pytest.mark.parametrize("shape,walls", [((12, 10, 15), False), ((10, 9, 22), False), ((10, 9, 22), True),
+                                         ((10, 9, 22), "porous")])
 def test_fp16_odd_and_even_rows_against_emulated_oracle(lib, shape, walls):
     """Unfolded (odd nx, or walls: single-cell march) and folded (even nx
     without walls: paired march) FP16 rows against the oracle with the same
-    storage rounding."""
+    storage rounding.  The obstacle geometry reads one-byte wall classes,
+    the random porous one (more distinct link words than classes) the
+    4-byte link words."""
     from paper_1601_01237_amd.sim import Sim
     say(f"fp16 {shape} walls={walls} x 12 vs emulated oracle")
     rho0 = inputs.sphere_droplet(shape, radius=3.5, seed=4)
     solid = None
-    if walls:
+    if walls == "porous":
+        solid = np.random.default_rng(8).uniform(size=shape) < 0.3
+        solid[0] = True
+        rho0[:, solid] = 0.0
+    elif walls:
         solid = np.zeros(shape, bool)
         solid[0] = True
         solid[5, 2:5, 3:9] = True
         rho0[:, solid] = 0.0
     p = olbm.Params(tau=(0.9, 0.7), G=((0.0, -1.2), (-1.2, 0.0)), rho_wall=(0.2, 0.1))
     sim = Sim(rho0, tau=p.tau, G=p.G, storage="fp16", solid=solid, rho_wall=p.rho_wall)
+    if walls:
+        assert (sim.wall_classes() > 0) == (walls is True)
     assert (sim.row_half > 0) == (shape[2] % 2 == 0 and not walls)
     sim.step(12)
     rho = sim.moments()[0].cpu().numpy()
