@@ -50,7 +50,8 @@ COMMON_SOURCES = ("pull.h", "cell.h", "buffer.h", "lattice.h", "launch.h", "api.
 KERNEL_SOURCES = {"step": ("march.hip", "march_pair.hip") + COMMON_SOURCES,
                   "reverse": ("adjoint_march.hip", "adjoint_cell.h") + COMMON_SOURCES}
 BYTES_PER_CELL = {"fp32": 304, "fp16": 160, "bf16": 160}
-SHAPES = {"128": (128, 128, 128), "512": (512, 512, 512), "walls": (192, 192, 384), "adjoint96": (96, 96, 96)}
+SHAPES = {"128": (128, 128, 128), "512": (512, 512, 512), "walls": (192, 192, 384), "adjoint96": (96, 96, 96),
+          "adjoint256": (256, 256, 256)}
 # Algorithmic bytes per cell of one reverse step: X_t and lam_{t+1} read once,
 # lam_t written once (FP32).
 ADJOINT_BYTES_PER_CELL = 456
@@ -408,7 +409,7 @@ def main(argv=None):
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
-    t.add_argument("--workload", default="128", choices=["128", "512", "walls", "adjoint96"])
+    t.add_argument("--workload", default="128", choices=["128", "512", "walls", "adjoint96", "adjoint256"])
     t.add_argument("--workload-key", default="128^3")
     t.add_argument("--storage", default="fp32")
     t.add_argument("--copy-gib", type=float, default=2.0)
