@@ -321,10 +321,13 @@ lbm_status lbm_set_placement(lbm_ctx *ctx, int32_t order, int32_t x_offset);
  * (the marches then read the words), -1 for a NULL context.  Host call. */
 int32_t lbm_wall_classes(const lbm_ctx *ctx);
 
-/* ---- Adjoint (reverse mode) of one step, FP32 storage -------------------
- * (16-bit storage forms and LBM_REGULARIZED3: LBM_ENOTSUP).  BGK (Eq. 2)
- * and the regularized operator (Eqs. 10-11, read as the second-order
- * projection of the non-equilibrium momentum flux).
+/* ---- Adjoint (reverse mode) of one step ---------------------------------
+ * (LBM_REGULARIZED3: LBM_ENOTSUP).  BGK (Eq. 2) and the regularized
+ * operator (Eqs. 10-11, read as the second-order projection of the
+ * non-equilibrium momentum flux).  With a 16-bit storage form the step
+ * differentiated is the FP32 step at the populations X_t decodes to (the
+ * values its own pull reads): the storage rounding is passed through as the
+ * identity, and the adjoint arrays are FP32 as for FP32 storage.
  * Let X_t be the stored state at t and L a scalar objective.  With
  * lam_{t+1} = dL/dX_{t+1} (device float, lbm_state_elems(nx, ny, nz,
  * LBM_FP32), in the layout of an FP32 stored state) this computes
@@ -337,8 +340,12 @@ int32_t lbm_wall_classes(const lbm_ctx *ctx);
  *   work   device scratch; work_bytes must be at least
  *          lbm_adjoint_work_bytes(ctx) for the current tiling (else
  *          LBM_EINVAL): 24 bytes (three FP64 partial sums) per workgroup of
- *          the reverse march.
- * lam_in and lam_out must not alias each other or x_t. */
+ *          the reverse march, and for 16-bit storage, from the next
+ *          multiple of 256 bytes on, an FP32 copy of X_t in the FP32 layout
+ *          (lbm_state_elems(nx, ny, nz, LBM_FP32) floats).  0 when the
+ *          lattice does not fit the FP32 layout (the calls answer
+ *          LBM_ENOTSUP).
+ * lam_in and lam_out must not alias each other, x_t or work. */
 size_t lbm_adjoint_work_bytes(const lbm_ctx *ctx);
 
 /* Tiling of the reverse march (results do not depend on it, up to the
@@ -357,16 +364,17 @@ lbm_status lbm_adjoint_step(lbm_ctx *ctx, const void *x_t, const float *lam_in,
 /* lbm_adjoint_step with the forward quantities of X_t read from fields (5*N
  * floats written by the lbm_step_fields call that advanced X_t) instead of
  * pulled again from X_t for the tile and its two-cell border: the same
- * results, bitwise, with less traffic.  fields must not alias x_t, lam_in or
- * lam_out (LBM_EINVAL); NULL fields: LBM_EINVAL. */
+ * results, bitwise, with less traffic.  FP32 storage only (LBM_ENOTSUP
+ * otherwise).  fields must not alias x_t, lam_in or lam_out (LBM_EINVAL);
+ * NULL fields: LBM_EINVAL. */
 lbm_status lbm_adjoint_step_fields(lbm_ctx *ctx, const void *x_t, const float *fields,
                                    const float *lam_in, float *lam_out, void *work,
                                    size_t work_bytes, double *dparams, double *drho0);
 
 /* dL/dX_T for an objective of the densities at time T: given
  * grad_rho (device float, 2*N, index a*N + c) = dL/drho^a(x, T), writes lam
- * (device float, an adjoint array, state layout) = dL/dX_T.  Solid cells get
- * zero. */
+ * (device float, an adjoint array: the FP32 state layout, whatever the
+ * storage) = dL/dX_T.  Solid cells get zero. */
 lbm_status lbm_adjoint_seed(lbm_ctx *ctx, const float *grad_rho, float *lam);
 
 /* Plain device-to-device copy of `bytes` bytes (a multiple of 16; both

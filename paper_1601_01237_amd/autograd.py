@@ -1,15 +1,19 @@
 """Reverse mode of the two-component step behind ``torch.autograd.Function``.
 
-``LBMFunction.apply(rho0, G, tau, steps, every, solid, rho_wall)`` runs
-``steps`` fused steps from the rest state of ``rho0`` and returns the species
-densities rho^a(x, T) as float32 (2, nz, ny, nx).  Its backward pass gives
-dL/drho0 (float64, same shape), dL/dG (tied G^{AB} = G^{BA}) and dL/dtau
-(tied tau_A = tau_B) for any scalar L of those densities.
+``LBMFunction.apply(rho0, G, tau, steps, every, solid, rho_wall, collision,
+storage)`` runs ``steps`` fused steps from the rest state of ``rho0`` and
+returns the species densities rho^a(x, T) as float32 (2, nz, ny, nx).  Its
+backward pass gives dL/drho0 (float64, same shape), dL/dG (tied G^{AB} =
+G^{BA}) and dL/dtau (tied tau_A = tau_B) for any scalar L of those densities.
+With 16-bit storage each reverse step is that of the FP32 step at the
+populations the stored state decodes to (the storage rounding is passed
+through as the identity).
 
 Backward is a checkpointed reverse sweep: the forward pass keeps the stored
 state every ``every`` steps; for each segment, last first, the states of the
-segment are recomputed from its checkpoint (each recomputed step also writes
-the densities and mixture velocity of the state it starts from) and the
+segment are recomputed from its checkpoint (with FP32 storage each
+recomputed step also writes the densities and mixture velocity of the state
+it starts from) and the
 library's adjoint step (transposed collision with the Eq. (7) gather,
 transposed pull streaming) carries dL/dX_{t+1} back to dL/dX_t.  All of it
 runs in liblbm.so.
@@ -36,11 +40,11 @@ def from_adjoint_layout(x, sim):
 
 
 class Reverse:
-    """Adjoint machinery of one Sim (FP32 storage)."""
+    """Adjoint machinery of one Sim.  The adjoint arrays are FP32 in the FP32
+    state layout whatever the storage; with 16-bit storage the workspace also
+    holds an FP32 copy of X_t and only the pulling reverse step exists."""
 
     def __init__(self, sim: Sim):
-        if sim.storage != "fp32":
-            raise ValueError("the adjoint is implemented for FP32 storage")
         self.sim = sim
         self.lib = sim.lib
         nbytes = int(self.lib.lbm_adjoint_work_bytes(sim.ctx))
@@ -99,7 +103,11 @@ def reverse_sweep(sim: Sim, ckpts, steps: int, every: int, grad_rho):
         states, fields = [], []
         for _ in range(s, e):
             states.append(sim.state.clone())
-            fields.append(sim.step_fields())
+            if sim.storage == "fp32":
+                fields.append(sim.step_fields())
+            else:
+                sim.step(1)
+                fields.append(None)
         for t in range(e - 1, s - 1, -1):
             lam, d = rev.step(states[t - s], lam, want_drho0=(t == 0), fields=fields[t - s])
             if d is not None:
@@ -113,10 +121,11 @@ class LBMFunction(torch.autograd.Function):
     """rho(T) = run(rho0; G, tau) with a hand-written adjoint (see module doc)."""
 
     @staticmethod
-    def forward(ctx, rho0, G, tau, steps, every=50, solid=None, rho_wall=(0.0, 0.0), collision="bgk"):
+    def forward(ctx, rho0, G, tau, steps, every=50, solid=None, rho_wall=(0.0, 0.0), collision="bgk",
+                storage="fp32"):
         g = float(G)
         t = float(tau)
-        sim = Sim(rho0.detach().double().cpu().numpy(), tau=(t, t), G=g, solid=solid,
+        sim = Sim(rho0.detach().double().cpu().numpy(), tau=(t, t), G=g, solid=solid, storage=storage,
                   rho_wall=rho_wall, device=rho0.device if rho0.is_cuda else "cuda:0", collision=collision)
         ckpts = forward_with_checkpoints(sim, int(steps), int(every))
         rho, _, _ = sim.moments()
@@ -133,4 +142,4 @@ class LBMFunction(torch.autograd.Function):
         ctx.sim.close()
         dev = ctx.rho0_device
         return (drho0.to(dev), torch.tensor(dG, dtype=torch.float64, device=dev),
-                torch.tensor(dtA + dtB, dtype=torch.float64, device=dev), None, None, None, None, None)
+                torch.tensor(dtA + dtB, dtype=torch.float64, device=dev), None, None, None, None, None, None)

@@ -68,6 +68,10 @@ double* static_partials(int dev) {
 
 }  // namespace
 
+// Supported layouts and sizes (defined with the layout entry points below).
+static bool layout_of(int32_t nx, int32_t ny, int32_t storage, Layout* L);
+static bool cells_fit(uint64_t n, size_t es);
+
 namespace {
 
 size_t elem_size(Storage s) { return s == Storage::F32 ? 4 : 2; }
@@ -110,9 +114,31 @@ Tiling aux_tiling(const lbm_ctx* c) {
   t.order = default_order(c);
   return t;
 }
+// The lattice in the FP32 layout: that of the adjoint arrays, and of the
+// state itself with FP32 storage.  nz = 0 when the lattice does not fit it.
+Grid fp32_grid(const lbm_ctx* c) {
+  if (c->storage == Storage::F32) return c->g;
+  Grid g = c->g;
+  Layout L;
+  if (!cells_fit(g.n, sizeof(float)) || !layout_of(g.nx, g.ny, LBM_FP32, &L)) {
+    g.nz = 0;
+    return g;
+  }
+  g.pstride = L.pstride;
+  g.half = 0;
+  g.brows = L.brows;
+  g.zstride = static_cast<uint32_t>(L.zstride);
+  return g;
+}
 Tiling adjoint_tiling(const lbm_ctx* c) {
-  const int shape = c->adj_shape >= 0 ? c->adj_shape : adjoint_auto_shape(c->g, c->links != nullptr, c->ph.regularized);
-  Tiling t = adjoint_march_tiling(c->g, shape, c->adj_zchunk);
+  const Grid g = fp32_grid(c);
+  Tiling t{};
+  if (g.nz < 1) {
+    t.blocks = -1;
+    return t;
+  }
+  const int shape = c->adj_shape >= 0 ? c->adj_shape : adjoint_auto_shape(g, c->links != nullptr, c->ph.regularized);
+  t = adjoint_march_tiling(g, shape, c->adj_zchunk);
   t.order = default_order(c);
   return t;
 }
@@ -482,9 +508,17 @@ static size_t adjoint_work(const Tiling& t) {
   return static_cast<size_t>(t.blocks > 0 ? t.blocks : 0) * 3 * sizeof(double);
 }
 
+// Workspace bytes of the partial sums, rounded up to 256 bytes: for 16-bit
+// storage the FP32 copy of X_t follows them.
+static size_t adjoint_partials_span(const Tiling& t) { return (adjoint_work(t) + 255) / 256 * 256; }
+
 size_t lbm_adjoint_work_bytes(const lbm_ctx* c) {
   if (!c) return 0;
-  return adjoint_work(adjoint_tiling(c));
+  const Tiling t = adjoint_tiling(c);
+  if (c->storage == Storage::F32) return adjoint_work(t);
+  const Grid g = fp32_grid(c);
+  if (g.nz < 1) return 0;
+  return adjoint_partials_span(t) + static_cast<size_t>(g.nz) * g.zstride * sizeof(float);
 }
 
 static lbm_status adjoint_step(lbm_ctx* c, const void* x_t, const float* fields, const float* lam_in,
@@ -493,13 +527,25 @@ static lbm_status adjoint_step(lbm_ctx* c, const void* x_t, const float* fields,
   if (work_bytes < lbm_adjoint_work_bytes(c)) return LBM_EINVAL;
   if (lam_in == lam_out || static_cast<const void*>(lam_in) == x_t || static_cast<const void*>(lam_out) == x_t)
     return LBM_EINVAL;
+  if (work == x_t || work == static_cast<const void*>(lam_in) || work == static_cast<void*>(lam_out))
+    return LBM_EINVAL;
   if (fields && (static_cast<const void*>(fields) == x_t || fields == lam_in || fields == lam_out))
     return LBM_EINVAL;
-  if (c->storage != Storage::F32 || c->ph.regularized == 2) return LBM_ENOTSUP;
+  if (c->ph.regularized == 2 || (fields && c->storage != Storage::F32)) return LBM_ENOTSUP;
   const Tiling t = adjoint_tiling(c);
   if (t.blocks <= 0) return LBM_ENOTSUP;
+  const Grid g = fp32_grid(c);
+  hipError_t e = hipSuccess;
+  const void* xs = x_t;
+  if (c->storage != Storage::F32) {
+    // the reverse step of the FP32 step at the populations X_t decodes to
+    float* wide = reinterpret_cast<float*>(static_cast<char*>(work) + adjoint_partials_span(t));
+    e = launch_widen_state(c->storage, c->g, g, c->ph, c->links, x_t, wide, c->stream);
+    if (e != hipSuccess) return from_hip(e);
+    xs = wide;
+  }
   AdjointIO io;
-  io.x_t = x_t;
+  io.x_t = xs;
   io.links = c->links;
   io.cls = c->cls;
   io.ltab = c->ltab;
@@ -508,7 +554,7 @@ static lbm_status adjoint_step(lbm_ctx* c, const void* x_t, const float* fields,
   io.partials = static_cast<double*>(work);
   io.drho0 = drho0;
   io.fields = fields;
-  hipError_t e = launch_adjoint_march(c->g, c->ph, t, io, c->stream);
+  e = launch_adjoint_march(g, c->ph, t, io, c->stream);
   if (e == hipSuccess) e = launch_finalize(io.partials, t.blocks, 3, -1, dparams, true, c->stream);
   return from_hip(e);
 }
@@ -526,7 +572,9 @@ lbm_status lbm_adjoint_step_fields(lbm_ctx* c, const void* x_t, const float* fie
 
 lbm_status lbm_adjoint_seed(lbm_ctx* c, const float* grad_rho, float* lam) {
   if (!c || !grad_rho || !lam) return LBM_EINVAL;
-  return from_hip(launch_adjoint_seed(c->g, c->links, grad_rho, lam, c->stream));
+  const Grid g = fp32_grid(c);  // the adjoint arrays' layout, whatever the storage
+  if (g.nz < 1) return LBM_ENOTSUP;
+  return from_hip(launch_adjoint_seed(g, c->links, grad_rho, lam, c->stream));
 }
 
 lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {

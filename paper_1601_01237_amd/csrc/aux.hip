@@ -135,6 +135,35 @@ __global__ void get_pop_kernel(const Grid g, const Phys ph, const uint32_t* __re
   }
 }
 
+// A 16-bit stored state rewritten as the FP32 stored state of the same
+// populations, in the FP32 layout g32: each value decoded and shifted back
+// (plus the rest population's residual), exactly as the 16-bit step's pull
+// reads it.  Wall cells carry no populations and get 0.
+template <Storage S>
+__global__ void widen_kernel(const Grid g, const Grid g32, const Phys ph, const uint32_t* __restrict__ links,
+                             const typename StorageTraits<S>::T* __restrict__ src, float* __restrict__ dst) {
+  using Tr = StorageTraits<S>;
+  using T = typename Tr::T;
+  for (uint64_t c = blockIdx.x * static_cast<uint64_t>(TPB) + threadIdx.x; c < g.n;
+       c += static_cast<uint64_t>(gridDim.x) * TPB) {
+    const Coord p = coord_of(c, g);
+    const bool solid = is_solid(links, c);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        float v = 0.0f;
+        if (!solid) {
+          v = Tr::decode(src[pm_at<T>(s, i, p, 0, 0, 0, g)]);
+          if (i == 0) v += Tr::decode(src[res_at<T>(s, p, g)]) * (1.0f / Tr::res_scale);
+          v += wshift(ph, s, i);
+        }
+        dst[pm_at<float>(s, i, p, 0, 0, 0, g32)] = v;
+      }
+    }
+  }
+}
+
 template <Storage S>
 __global__ void set_pop_kernel(const Grid g, const Phys ph, const uint32_t* __restrict__ links,
                                const float* __restrict__ f, typename StorageTraits<S>::T* __restrict__ dst) {
@@ -286,6 +315,24 @@ hipError_t launch_get_populations(Storage s, const Grid& g, const Phys& ph, cons
     case Storage::BF16:
       hipLaunchKernelGGL(get_pop_kernel<Storage::BF16>, gr, bl, 0, st, g, ph, links, static_cast<const uint16_t*>(src), f);
       break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_widen_state(Storage s, const Grid& g, const Grid& g32, const Phys& ph, const uint32_t* links,
+                              const void* src, float* dst, hipStream_t st) {
+  const dim3 gr(grid_for(g.n)), bl(TPB);
+  switch (s) {
+    case Storage::F16:
+      hipLaunchKernelGGL(widen_kernel<Storage::F16>, gr, bl, 0, st, g, g32, ph, links,
+                         static_cast<const _Float16*>(src), dst);
+      break;
+    case Storage::BF16:
+      hipLaunchKernelGGL(widen_kernel<Storage::BF16>, gr, bl, 0, st, g, g32, ph, links,
+                         static_cast<const uint16_t*>(src), dst);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

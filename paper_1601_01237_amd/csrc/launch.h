@@ -164,6 +164,10 @@ hipError_t launch_get_populations(Storage s, const Grid& g, const Phys& ph, cons
                                   const void* src, float* f, hipStream_t st);
 hipError_t launch_set_populations(Storage s, const Grid& g, const Phys& ph, const uint32_t* links,
                                   const float* f, void* dst, hipStream_t st);
+// A 16-bit stored state (layout g) as an FP32 stored state (layout g32, the
+// same lattice) of the populations its pull reads; 16-bit storage only.
+hipError_t launch_widen_state(Storage s, const Grid& g, const Grid& g32, const Phys& ph, const uint32_t* links,
+                              const void* src, float* dst, hipStream_t st);
 // Sums the per-workgroup partials (blocks x nvals) into out[0..nvals); entry
 // max_index (-1: none) takes the maximum instead of the sum.
 hipError_t launch_finalize(const double* partials, int blocks, int nvals, int max_index, double* out,

@@ -109,7 +109,7 @@ class Sim:
                            int(self.lib.lbm_plane_stride(nx, ny, _lib.FP32)), layout_rows("fp32"))
         self.lam_elems = int(self.lib.lbm_state_elems(nx, ny, nz, _lib.FP32))
         self.row_half = int(self.lib.lbm_row_half(nx, code, int(solid is not None)))
-        # (the adjoint arrays are FP32 and only used with FP32 storage)
+        # (the adjoint arrays are FP32, in the FP32 layout whatever the storage)
         if min(self.pstride, *self.layout, self.state_elems, self.row_half) < 0:
             raise ValueError(f"grid {self.shape} is not supported")
 

@@ -6,6 +6,8 @@ f_t = pull(X_t) and S the pull streaming; in oracle terms that is
 ``stream_adjoint(collide_adjoint(f_t, lam))``.
 """
 
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -315,8 +317,9 @@ def test_adjoint_step_96cube_all_cells(lib, collision, tau, fields):
 
 def test_adjoint_workspace_size_and_checks(lib):
     """The workspace holds three FP64 partial sums per workgroup of the
-    reverse march, whatever the collision; a workspace one byte short,
-    aliased arrays and 16-bit storage are refused before anything is
+    reverse march, whatever the collision, and for 16-bit storage an FP32
+    copy of X_t after them; a workspace one byte short, aliased arrays and
+    the third-order regularized reading are refused before anything is
     launched."""
     import ctypes
     from paper_1601_01237_amd.sim import Sim
@@ -344,10 +347,22 @@ def test_adjoint_workspace_size_and_checks(lib):
     for sim in sims.values():
         sim.close()
     h = Sim(rho0, storage="fp16")
-    work16 = torch.empty(int(lib.lbm_adjoint_work_bytes(h.ctx)), dtype=torch.uint8, device="cuda")
+    h.set_adjoint_tiling(2, 2)
+    wb16 = int(lib.lbm_adjoint_work_bytes(h.ctx))
+    assert wb16 == 256 + 4 * h.lam_elems  # 144 bytes of partial sums, rounded up, then X_t in FP32
+    work16 = torch.empty(wb16, dtype=torch.uint8, device="cuda")
     assert lib.lbm_adjoint_step(h.ctx, p(h.state), p(lam_in), p(lam_out), p(work16),
-                                ctypes.c_size_t(work16.numel()), p(dparams), None) == -5  # LBM_ENOTSUP
+                                ctypes.c_size_t(wb16 - 1), p(dparams), None) == -1
+    assert lib.lbm_adjoint_step(h.ctx, p(h.state), p(lam_in), p(lam_out), p(work16),
+                                ctypes.c_size_t(wb16), p(dparams), None) == 0
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(lam_out).all())
     h.close()
+    r3 = Sim(rho0, collision="regularized3")
+    work3 = torch.empty(int(lib.lbm_adjoint_work_bytes(r3.ctx)), dtype=torch.uint8, device="cuda")
+    assert lib.lbm_adjoint_step(r3.ctx, p(r3.state), p(lam_in), p(lam_out), p(work3),
+                                ctypes.c_size_t(work3.numel()), p(dparams), None) == -5  # LBM_ENOTSUP
+    r3.close()
 
 
 @pytest.mark.parametrize("collision,walls", [("bgk", False), ("regularized", True)])
@@ -462,3 +477,91 @@ def test_step_fields_refusals(lib):
     assert s.lib.lbm_step_fields(s.ctx, ctypes.c_void_p(s.state.data_ptr())) == -1
     assert s.t == 0
     s.close()
+
+
+@pytest.mark.parametrize("collision", ["bgk", "regularized"])
+@pytest.mark.parametrize("storage,walls", [("fp16", None), ("bf16", None), ("fp16", "obstacle"), ("bf16", "porous")])
+def test_16bit_reverse_step(lib, storage, walls, collision):
+    """The reverse step of a 16-bit context is the FP32 reverse step at the
+    populations its stored state decodes to: bitwise that of an FP32 context
+    holding those populations, and the oracle's transpose at them.  Folded
+    rows (even nx, no walls) and unfolded rows, class bytes and link words."""
+    from paper_1601_01237_amd.autograd import Reverse, from_adjoint_layout, to_adjoint_layout
+    from paper_1601_01237_amd.sim import Sim
+    say(f"16-bit reverse step {storage} walls={walls} {collision}")
+    shape = (7, 9, 70)
+    solid = None
+    if walls == "obstacle":
+        solid = np.zeros(shape, bool)
+        solid[0] = True
+        solid[3, 2:6, 10:30] = True
+    elif walls == "porous":
+        solid = np.random.default_rng(23).uniform(size=shape) < 0.3
+        solid[0] = True
+    f, rho = _random_state(shape, 5, solid)
+    if solid is not None:
+        rho[:, solid] = 0.0
+    p = olbm.Params(tau=(0.8, 1.3), G=((0.0, -1.4), (-0.6, 0.0)), rho_wall=(0.15, 0.35), collision=collision)
+    kw = dict(tau=p.tau, G=p.G, rho_wall=p.rho_wall, solid=solid, collision=collision)
+    s16 = Sim(rho, storage=storage, **kw)
+    assert (s16.row_half > 0) == (walls is None)
+    s16.set_populations(torch.from_numpy(f.astype(np.float32)))
+    f16 = s16.populations().cpu().numpy()          # what the 16-bit step pulls
+    s32 = Sim(rho, storage="fp32", **kw)
+    s32.set_populations(torch.from_numpy(f16))
+    assert np.array_equal(s32.populations().cpu().numpy(), f16)
+    lam1 = np.random.default_rng(6).normal(size=f.shape)
+    if solid is not None:
+        lam1[:, :, solid] = 0.0
+    lam1 = lam1.astype(np.float32)
+    lam_in = to_adjoint_layout(torch.from_numpy(lam1).cuda(), s32)
+    r16, r32 = Reverse(s16), Reverse(s32)
+    assert r16.work.numel() > r32.work.numel()     # the FP32 copy of X_t
+    a, da = r16.step(s16.state, lam_in, want_drho0=True)
+    b, db = r32.step(s32.state, lam_in, want_drho0=True)
+    torch.cuda.synchronize()
+    live = s32.live_mask(s32.lam_layout)
+    assert torch.equal(a[live], b[live]) and torch.equal(da, db)
+    np.testing.assert_array_equal(r16.dparams.cpu().numpy(), r32.dparams.cpu().numpy())
+    got = from_adjoint_layout(a, s32).cpu().numpy()
+    mu, _, _ = oadj.collide_adjoint(f16.astype(np.float64), lam1.astype(np.float64), p, solid)
+    want = oadj.stream_adjoint(mu, solid)
+    e = rel_err(got, want)
+    assert e < 1e-5, e
+    # the fields path stays FP32-only
+    fl = torch.zeros(5 * s16.n, dtype=torch.float32, device="cuda")
+    assert s16.lib.lbm_adjoint_step_fields(
+        s16.ctx, ctypes.c_void_p(s16.state.data_ptr()), ctypes.c_void_p(fl.data_ptr()),
+        ctypes.c_void_p(lam_in.data_ptr()), ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(r16.work.data_ptr()),
+        ctypes.c_size_t(r16.work.numel()), ctypes.c_void_p(r16.dparams.data_ptr()), None) == -5
+    s16.close()
+    s32.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("fp16", 1e-3), ("bf16", 1e-2)])
+def test_16bit_calibration_gradient_16cube(lib, storage, tol):
+    """The calibration gradient of a 16-bit run (16^3, 200 steps, checkpoints
+    every 50) against the FP64 oracle's gradient of the exact run: the
+    forward's storage rounding (2^-11 of a stored deviation for FP16, 2^-8
+    for BF16, per step) is all that separates them.  Measured: at most 6e-5
+    (FP16) and 3e-4 (BF16); the bounds sit an order of magnitude above,
+    the FP16 one ten times inside the 1e-2 the FP16 forward is held to."""
+    from paper_1601_01237_amd.autograd import LBMFunction
+    say(f"16-bit calibration gradient 16^3 x 200 {storage}")
+    n, steps, every = 16, 200, 50
+    rho0, target = _calibration_inputs(n)
+    G, tau = -1.0, 1.0
+    r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
+    Gt = torch.tensor(G, dtype=torch.float64, requires_grad=True)
+    Tt = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
+    rho = LBMFunction.apply(r0, Gt, Tt, steps, every, None, (0.0, 0.0), "bgk", storage)
+    tgt = torch.tensor(target, dtype=torch.float32, device="cuda")
+    L = 0.5 * ((rho[0].double() - tgt.double()) ** 2).sum()
+    L.backward()
+    p = olbm.Params(tau=(tau, tau), G=((0.0, G), (G, 0.0)))
+    L_ref, dG_ref, dtau_ref, drho0_ref = oadj.loss_and_gradient(rho0, p, steps, target)
+    e_G = abs(float(Gt.grad) - dG_ref) / abs(dG_ref)
+    e_t = abs(float(Tt.grad) - dtau_ref) / abs(dtau_ref)
+    e_r = rel_err(r0.grad.cpu().numpy(), drho0_ref)
+    say(f"16^3 {storage} calibration: dL/dG {e_G:.1e}, dL/dtau {e_t:.1e}, dL/drho0 {e_r:.1e}")
+    assert e_G < tol and e_t < tol and e_r < tol, (e_G, e_t, e_r)
