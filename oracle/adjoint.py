@@ -39,7 +39,11 @@ their form with two substitutions: the population that multiplies
 E_j(rho^a, u) is mu_j^a = -c_j c_j : Pi_bar^a instead of
 (omega_a - 1) lam*_j^a, and the direct term of lam_k^a is c_k c_k : Pi_bar^a
 instead of (1 - omega_a) lam*_k^a.  dL/dtau_a = sum_x sum_i lam*_i^a N_i^a /
-tau_a^2.  Both operators are written below with mu:
+tau_a^2.  The third-order reading adds w_i H_i . q^a / N to N_i^a (energy-flux
+polynomials H, their norm N, q^a = sum_j H_j (f_j^a - E_j(rho^a, u))), which
+is linear in f - E(rho, u) as Pi^a is: with q_bar^a = (1 - omega_a) sum_i
+lam*_i^a w_i H_i / N, mu_j^a gains -H_j . q_bar^a and the direct term
+H_k . q_bar^a.  All three operators are written below with mu:
 
     rho_bar^a = sum_i w_i [mu_i^a P_i(u) + lam*_i^a P_i(v^a)]
     u_bar     = sum_a rho^a sum_i w_i [mu_i^a dP_i(u) + lam*_i^a dP_i(v^a)]
@@ -88,9 +92,13 @@ def stream_adjoint(lam, solid=None):
     return out
 
 
-def _projection_weights(lam_a, omega):
+def _projection_weights(lam_a, omega, order=2):
     """mu_j = -c_j c_j : Pi_bar of the regularized operator, with
-    Pi_bar = (1 - omega) sum_i lam_i w_i (c_i c_i - T0 I) / (2 T0^2)."""
+    Pi_bar = (1 - omega) sum_i lam_i w_i (c_i c_i - T0 I) / (2 T0^2); with
+    the third-order reading also -H_j . q_bar, where H are the energy-flux
+    polynomials of :func:`oracle.lbm.energy_flux_hermite`, N their norm and
+    q_bar = (1 - omega) sum_i lam_i w_i H_i / N (the pullback through the
+    coefficients q = sum_j H_j (f_j - E_j))."""
     shape = lam_a.shape[1:]
     pbar = np.zeros((3, 3) + shape, dtype=lam_a.dtype)
     for i in range(Q):
@@ -103,18 +111,28 @@ def _projection_weights(lam_a, omega):
     mu = np.empty_like(lam_a)
     for j in range(Q):
         mu[j] = -sum(C[j, a] * C[j, b] * pbar[a, b] for a in range(3) for b in range(3))
+    if order == 3:
+        he = lbm.energy_flux_hermite()
+        norm = float(np.sum(W * he[:, 0] ** 2))
+        qbar = [(1.0 - omega) / norm * sum(lam_a[i] * W[i] * he[i, a] for i in range(Q) if he[i, a] != 0.0)
+                for a in range(3)]
+        for j in range(Q):
+            mu[j] = mu[j] - sum(he[j, a] * qbar[a] for a in range(3) if he[j, a] != 0.0)
+    elif order != 2:
+        raise ValueError(order)
     return mu
 
 
 def collide_adjoint(f, lam_star, p: Params, solid=None):
-    """Transpose of :func:`oracle.lbm.collide` at state ``f`` (BGK or
-    regularized collision).
+    """Transpose of :func:`oracle.lbm.collide` at state ``f`` (BGK or the
+    regularized collision, second- or third-order reading).
 
     Returns ``(lam, dG, dtau)``: lam = dL/df (same shape as f), dG a (2, 2)
     array of dL/dG^{ab} and dtau a length-2 array of dL/dtau_a.
     """
-    if p.collision not in ("bgk", "regularized"):
+    if p.collision not in ("bgk", "regularized", "regularized3"):
         raise ValueError(p.collision)
+    order = 3 if p.collision == "regularized3" else 2
     m = lbm.macroscopic(f, p, solid)
     fluid, rho_s, rho, u = m["fluid"], m["rho_s"], m["rho"], m["u"]
     shape = f.shape[2:]
@@ -136,8 +154,8 @@ def collide_adjoint(f, lam_star, p: Params, solid=None):
             mu[a] = (omega - 1.0) * lam_star[a]
             part = f[a] - lbm.equilibrium(rho_s[a], u)        # df*/dtau = (f - E) / tau^2
         else:
-            mu[a] = _projection_weights(lam_star[a], omega)
-            part = lbm.regularized_neq(f[a], rho_s[a], u)      # df*/dtau = N / tau^2
+            mu[a] = _projection_weights(lam_star[a], omega, order)
+            part = lbm.regularized_neq(f[a], rho_s[a], u, order)  # df*/dtau = N / tau^2
         for i in range(Q):
             ci = C[i]
             cu = ci[0] * u[0] + ci[1] * u[1] + ci[2] * u[2]

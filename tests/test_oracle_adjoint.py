@@ -33,7 +33,7 @@ def _walls(shape):
     return solid
 
 
-@pytest.mark.parametrize("collision", ["bgk", "regularized"])
+@pytest.mark.parametrize("collision", ["bgk", "regularized", "regularized3"])
 @pytest.mark.parametrize("walls", [False, True])
 def test_one_step_dot_product(walls, collision):
     shape = (5, 4, 6)
@@ -53,7 +53,7 @@ def test_one_step_dot_product(walls, collision):
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
 
 
-@pytest.mark.parametrize("collision", ["bgk", "regularized"])
+@pytest.mark.parametrize("collision", ["bgk", "regularized", "regularized3"])
 @pytest.mark.parametrize("walls", [False, True])
 def test_one_step_parameter_derivatives(walls, collision):
     shape = (4, 5, 6)
