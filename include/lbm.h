@@ -219,9 +219,8 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
  * rho~^A, rho~^B, u_x, u_y, u_z of every cell c, with rho~^a = rho_s^a and
  * u = 0 on wall cells.  Passed to lbm_adjoint_step_fields with the same X_t,
  * it replaces the reverse march's own pull of the tile border.  FP32
- * storage and the BGK or second-order regularized collision only
- * (LBM_ENOTSUP otherwise); fields must not alias a state buffer
- * (LBM_EINVAL).  t += 1. */
+ * storage only (LBM_ENOTSUP otherwise); fields must not alias a state
+ * buffer (LBM_EINVAL).  t += 1. */
 lbm_status lbm_step_fields(lbm_ctx *ctx, float *fields);
 
 /* Observables of the current time t (Eqs. 4-9).  Any output may be NULL.
@@ -322,9 +321,9 @@ lbm_status lbm_set_placement(lbm_ctx *ctx, int32_t order, int32_t x_offset);
 int32_t lbm_wall_classes(const lbm_ctx *ctx);
 
 /* ---- Adjoint (reverse mode) of one step ---------------------------------
- * (LBM_REGULARIZED3: LBM_ENOTSUP).  BGK (Eq. 2) and the regularized
- * operator (Eqs. 10-11, read as the second-order projection of the
- * non-equilibrium momentum flux).  With a 16-bit storage form the step
+ * BGK (Eq. 2) and the regularized operator (Eqs. 10-11) in both readings:
+ * the projection of the non-equilibrium momentum flux (LBM_REGULARIZED) and
+ * that plus the energy flux (LBM_REGULARIZED3).  With a 16-bit storage form the step
  * differentiated is the FP32 step at the populations X_t decodes to (the
  * values its own pull reads): the storage rounding is passed through as the
  * identity, and the adjoint arrays are FP32 as for FP32 storage.

@@ -150,6 +150,67 @@ __device__ __forceinline__ void adjoint_species_reg(int s, const float lam[Q], c
   A.ubar[2] -= 2.0f * r * pz;
 }
 
+// Third-order reading of the filter (R22): N_i also holds w_i H_i . q / N
+// with the energy-flux polynomials H_i = h_k c_i (h_k = -2 T0 on the faces,
+// T0 on the edges; H_0 = 0), N = 2 T0^3 their norm and q = sum_j H_j (f_j -
+// E_j(rho, u)), linear in f - E(rho, u) as Pi is.  With B_E = sum_i lam_i w_i
+// H_i / N and qb = (1 - w) B_E, dL = qb . dq adds
+//   to dL/df_k   H_k . qb               (odd: +- h_k c_k . qb per pair)
+//   through the weights -H_j . qb of E_j(rho, u): to rho_bar and u_bar the
+//   pullback of sum_j w_j (-H_j . qb) rho P_j(u) (only the odd part of P)
+// and dL/dtau_a gains (q . B_E) / tau^2.
+__device__ __forceinline__ constexpr float pair_h(int k) { return k < 3 ? -2.0f * T0F : T0F; }
+
+__device__ __forceinline__ void adjoint_species_energy(int s, const float lam[Q], const float f[Q], const Local& L,
+                                                       const Phys& ph, AdjointSums& A, float qb[3]) {
+  const float* u = L.u;
+  const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  float cu[9];
+  pair_dots(u[0], u[1], u[2], cu);
+  const float r = L.rho[s];
+  float be[3] = {0.f, 0.f, 0.f}, q[3] = {0.f, 0.f, 0.f}, odd[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const float w = pair_w(k);
+    odd[k] = cu[k] * (3.0f - 4.5f * uu + 4.5f * cu[k] * cu[k]);  // (P_k+ - P_k-) / 2 at u
+    const float dl = (lam[2 * k + 1] - lam[2 * k + 2]) * (w * pair_h(k));
+    const float dq = pair_h(k) * ((f[2 * k + 1] - f[2 * k + 2]) - 2.0f * w * r * odd[k]);
+    if (pair_cx(k)) { be[0] += pair_cx(k) * dl; q[0] += pair_cx(k) * dq; }
+    if (pair_cy(k)) { be[1] += pair_cy(k) * dl; q[1] += pair_cy(k) * dq; }
+    if (pair_cz(k)) { be[2] += pair_cz(k) * dl; q[2] += pair_cz(k) * dq; }
+  }
+  constexpr float inv_norm = 1.0f / (2.0f * T0F * T0F * T0F);
+  const float om = ph.omega[s];
+  const float keep = 1.0f - om;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    be[a] *= inv_norm;
+    qb[a] = keep * be[a];
+  }
+  A.dtau[s] += om * om * (q[0] * be[0] + q[1] * be[1] + q[2] * be[2]);
+  float ub[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const float cq = pair_cx(k) * qb[0] + pair_cy(k) * qb[1] + pair_cz(k) * qb[2];
+    const float m2w = -2.0f * pair_h(k) * cq * pair_w(k);  // 2 w_k times the weight of E_k+ (E_k- takes minus it)
+    A.rbar[s] += m2w * odd[k];
+    const float e = 3.0f - 4.5f * uu + 13.5f * cu[k] * cu[k];
+    const float o = 9.0f * cu[k];
+    if (pair_cx(k)) ub[0] += m2w * pair_cx(k) * e;
+    if (pair_cy(k)) ub[1] += m2w * pair_cy(k) * e;
+    if (pair_cz(k)) ub[2] += m2w * pair_cz(k) * e;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ub[a] -= m2w * o * u[a];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) A.ubar[a] += r * ub[a];
+}
+
+// H_k . qb for pair k's first direction (the second takes minus it).
+__device__ __forceinline__ float pair_hq(int k, const float qb[3]) {
+  return pair_h(k) * (pair_cx(k) * qb[0] + pair_cy(k) * qb[1] + pair_cz(k) * qb[2]);
+}
+
 // c_k c_k : Pbar for pair k (both of its directions).
 __device__ __forceinline__ float pair_quad(int k, const float pb[6]) {
   switch (k) {

@@ -123,7 +123,7 @@ __device__ __forceinline__ void read_fields(const float* __restrict__ fields, ui
   u[2] = fields[4 * n + c];
 }
 
-template <bool WALLS, bool REG, bool FIELDS, int BXT, int ROWS, int HW>
+template <bool WALLS, int REG, bool FIELDS, int BXT, int ROWS, int HW>
 __global__ void __launch_bounds__(BXT * ROWS + 64 * HW)
 adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const AdjointIO io) {
   using Sh = AdjShape<BXT, ROWS, HW>;
@@ -135,7 +135,7 @@ adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const Adjoint
   // planes later) in LDS, one lane's values for its own use only, two plane
   // slots; read again from memory at stage C they mostly missed the L2.  The
   // 512-cell tiles do not have the LDS for it and read them again.
-  constexpr bool STASH = !REG && Sh::NOWN <= 256;
+  constexpr bool STASH = REG == 0 && Sh::NOWN <= 256;
   __shared__ float stash[STASH ? 2 * 2 * Q * Sh::NOWN : 1];
 
   const int tid = threadIdx.x;
@@ -171,7 +171,7 @@ adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const Adjoint
     // a, b (and Pbar) from B (used by C two planes later).
     uint32_t lk_a = 0u, lk_b = 0u, lk_c1 = 0u, lk_c2 = 0u;
     float u_a[3] = {0.f, 0.f, 0.f}, u_b[3] = {0.f, 0.f, 0.f};
-    constexpr int NM = REG ? 17 : 5;  // a^A, a^B, b xyz (+ Pbar^A, Pbar^B)
+    constexpr int NM = REG == 2 ? 23 : (REG ? 17 : 5);  // a^A, a^B, b xyz (+ Pbar^A, Pbar^B (+ qb^A, qb^B))
     // At the top of iteration k: m1 holds B's values of plane z0 - 4 + k,
     // m2 those of plane z0 - 5 + k (the plane of stage C).
     float m1[NM], m2[NM];
@@ -207,7 +207,7 @@ adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const Adjoint
       // B's follow in B: holding both would not fit the register budget).
       // Measured at 96^3 with the forward fields: 0.141 -> 0.132 ms.  The
       // regularized transpose has no registers to spare for it.
-      constexpr bool PRE = !REG;
+      constexpr bool PRE = REG == 0;
       float pre_lam[Q], pre_f[Q];
       if (PRE && k >= 2 && k <= zc + 3 && !(WALLS && (lk_b & 1u))) {
         const int zq = wrap(z0 - 3 + k, g.nz);
@@ -264,8 +264,14 @@ adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const Adjoint
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
               float mu;
-              if constexpr (REG) {
+              if constexpr (REG != 0) {
                 mu = i == 0 ? 0.0f : pair_quad((i - 1) >> 1, &m2[5 + 6 * s]);
+                if constexpr (REG == 2) {
+                  if (i != 0) {
+                    const float hq = pair_hq((i - 1) >> 1, &m2[17 + 3 * s]);
+                    mu += (i & 1) ? hq : -hq;
+                  }
+                }
               } else if constexpr (STASH) {
                 mu = stash[(((k - 1) & 1) * 2 * Q + s * Q + i) * Sh::NOWN + tid];  // slot of plane z0 - 5 + k
               } else {
@@ -311,7 +317,7 @@ adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const Adjoint
           AdjointSums S;
 #pragma unroll
           for (int c = 0; c < 3; ++c) S.ubar[c] = 0.0f;
-          float pb[2][6];
+          float pb[2][6], qe[2][3];
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
             float lam[Q], fs[Q];
@@ -326,9 +332,10 @@ adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const Adjoint
               for (int i = 0; i < Q; ++i) lam[i] = buf_load<float>(rl, col_b, static_cast<uint32_t>(s * Q + i) * ppb);
               pull_species<Storage::F32, WALLS>(rc, ppb, col, lk_b, ws0, s, fs);
             }
-            if constexpr (REG) {
+            if constexpr (REG != 0) {
               adjoint_species<true>(s, 0.0f, lam, L, ph, S);
               adjoint_species_reg(s, lam, fs, L, ph, S, pb[s]);
+              if constexpr (REG == 2) adjoint_species_energy(s, lam, fs, L, ph, S, qe[s]);
             } else {
               float dot = lam[0] * fs[0];
 #pragma unroll
@@ -353,11 +360,18 @@ adjoint_march_kernel(const Grid g, const Phys ph, const Tiling tl, const Adjoint
             acc[1] += a3[1];
             acc[2] += a3[2];
           }
-          if constexpr (REG) {
+          if constexpr (REG != 0) {
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
               mo[5 + c] = pb[0][c];
               mo[11 + c] = pb[1][c];
+            }
+          }
+          if constexpr (REG == 2) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              mo[17 + c] = qe[0][c];
+              mo[20 + c] = qe[1][c];
             }
           }
         }
@@ -478,7 +492,7 @@ struct AdjTile {
 };
 constexpr AdjTile ADJ_TILES[ADJOINT_SHAPES] = {{64, 8, 3}, {32, 16, 2}, {32, 8, 2}, {64, 4, 3}};
 
-template <bool WALLS, bool REG, bool FIELDS, int BXT, int ROWS, int HW>
+template <bool WALLS, int REG, bool FIELDS, int BXT, int ROWS, int HW>
 hipError_t launch_shape(const Grid& g, const Phys& ph, const Tiling& t, const AdjointIO& io, hipStream_t st) {
   using Sh = AdjShape<BXT, ROWS, HW>;
   hipLaunchKernelGGL((adjoint_march_kernel<WALLS, REG, FIELDS, BXT, ROWS, HW>), dim3(t.blocks), dim3(Sh::NT), 0, st,
@@ -486,7 +500,7 @@ hipError_t launch_shape(const Grid& g, const Phys& ph, const Tiling& t, const Ad
   return hipGetLastError();
 }
 
-template <bool WALLS, bool REG, bool FIELDS>
+template <bool WALLS, int REG, bool FIELDS>
 hipError_t launch_shapes(const Grid& g, const Phys& ph, const Tiling& t, const AdjointIO& io, hipStream_t st) {
   switch (t.tile) {
     case 0: return launch_shape<WALLS, REG, FIELDS, 64, 8, 3>(g, ph, t, io, st);
@@ -497,7 +511,7 @@ hipError_t launch_shapes(const Grid& g, const Phys& ph, const Tiling& t, const A
   }
 }
 
-template <bool WALLS, bool REG>
+template <bool WALLS, int REG>
 hipError_t launch_variant(const Grid& g, const Phys& ph, const Tiling& t, const AdjointIO& io, hipStream_t st) {
   return io.fields ? launch_shapes<WALLS, REG, true>(g, ph, t, io, st) : launch_shapes<WALLS, REG, false>(g, ph, t, io, st);
 }
@@ -572,12 +586,16 @@ int adjoint_auto_shape(const Grid& g, bool walls, int collision) {
 hipError_t launch_adjoint_march(const Grid& g, const Phys& ph, const Tiling& t, const AdjointIO& io,
                                 hipStream_t st) {
   if (t.blocks <= 0 || !io.x_t || !io.lam_in || !io.lam_out || !io.partials) return hipErrorInvalidValue;
-  if (io.links) {
-    return ph.regularized ? launch_variant<true, true>(g, ph, t, io, st)
-                          : launch_variant<true, false>(g, ph, t, io, st);
+  // ph.regularized: 0 BGK, 1 second-order, 2 third-order reading of the filter
+  switch (ph.regularized + (io.links ? 3 : 0)) {
+    case 0: return launch_variant<false, 0>(g, ph, t, io, st);
+    case 1: return launch_variant<false, 1>(g, ph, t, io, st);
+    case 2: return launch_variant<false, 2>(g, ph, t, io, st);
+    case 3: return launch_variant<true, 0>(g, ph, t, io, st);
+    case 4: return launch_variant<true, 1>(g, ph, t, io, st);
+    case 5: return launch_variant<true, 2>(g, ph, t, io, st);
+    default: return hipErrorInvalidValue;
   }
-  return ph.regularized ? launch_variant<false, true>(g, ph, t, io, st)
-                        : launch_variant<false, false>(g, ph, t, io, st);
 }
 
 }  // namespace lbm

@@ -389,7 +389,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t n) {
 lbm_status lbm_step_fields(lbm_ctx* c, float* fields) {
   if (!c || !fields) return LBM_EINVAL;
   if (static_cast<void*>(fields) == c->buf[0] || static_cast<void*>(fields) == c->buf[1]) return LBM_EINVAL;
-  if (c->storage != Storage::F32 || c->ph.regularized == 2) return LBM_ENOTSUP;
+  if (c->storage != Storage::F32) return LBM_ENOTSUP;
   const Tiling t = step_tiling(c);
   if (t.blocks <= 0) return LBM_ENOTSUP;
   MarchIO io;
@@ -531,7 +531,7 @@ static lbm_status adjoint_step(lbm_ctx* c, const void* x_t, const float* fields,
     return LBM_EINVAL;
   if (fields && (static_cast<const void*>(fields) == x_t || fields == lam_in || fields == lam_out))
     return LBM_EINVAL;
-  if (c->ph.regularized == 2 || (fields && c->storage != Storage::F32)) return LBM_ENOTSUP;
+  if (fields && c->storage != Storage::F32) return LBM_ENOTSUP;
   const Tiling t = adjoint_tiling(c);
   if (t.blocks <= 0) return LBM_ENOTSUP;
   const Grid g = fp32_grid(c);

@@ -490,11 +490,11 @@ static hipError_t launch_tile(const Grid& g, const Phys& ph, const Tiling& t, co
     if (t.tile != 0) return hipErrorInvalidValue;
     return launch_shape<S, WALLS, M, 64, 8, 3>(g, ph, t, io, st);
   } else if constexpr (M == Mode::StepFields && S == Storage::F32) {
-    // the operators the reverse step has
     if (!io.fields) return hipErrorInvalidValue;
     switch (ph.regularized) {
       case 0: return launch_step<S, WALLS, 0, M>(g, ph, t, io, st);
       case 1: return launch_step<S, WALLS, 1, M>(g, ph, t, io, st);
+      case 2: return launch_step<S, WALLS, 2, M>(g, ph, t, io, st);
       default: return hipErrorInvalidValue;
     }
   } else {

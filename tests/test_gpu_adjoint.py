@@ -32,7 +32,7 @@ def _random_state(shape, seed, solid=None):
     return f.astype(np.float32).astype(np.float64), rho
 
 
-@pytest.mark.parametrize("collision", ["bgk", "regularized"])
+@pytest.mark.parametrize("collision", ["bgk", "regularized", "regularized3"])
 @pytest.mark.parametrize("walls", [None, "obstacle", "porous"])
 def test_one_adjoint_step_matches_oracle(lib, walls, collision):
     """The obstacle geometry takes the one-byte wall classes, the random
@@ -79,7 +79,8 @@ def test_one_adjoint_step_matches_oracle(lib, walls, collision):
     if collision == "bgk":
         part = [f[a] - olbm.equilibrium(m["rho_s"][a], m["u"]) for a in range(2)]
     else:
-        part = [olbm.regularized_neq(f[a], m["rho_s"][a], m["u"]) for a in range(2)]
+        order = 3 if collision == "regularized3" else 2
+        part = [olbm.regularized_neq(f[a], m["rho_s"][a], m["u"], order) for a in range(2)]
     scale_tau = [np.sum(np.abs(lam1[a] * part[a])) / p.tau[a] ** 2 for a in range(2)]
     assert abs(d[0] - (dG[0, 1] + dG[1, 0])) <= 1e-4 * abs(dG[0, 1] + dG[1, 0]), (d[0], dG)
     assert abs(d[1] - dtau[0]) <= 1e-6 * scale_tau[0], (d[1], dtau, scale_tau)
@@ -167,28 +168,30 @@ def test_calibration_gradient_16cube_matches_fp64_oracle(lib):
     assert e_G < 1e-3 and e_t < 1e-3 and e_r < 1e-3, (e_G, e_t, e_r)
 
 
-def test_regularized_calibration_gradient_16cube_matches_fp64_oracle(lib):
+@pytest.mark.parametrize("collision", ["regularized", "regularized3"])
+def test_regularized_calibration_gradient_16cube_matches_fp64_oracle(lib, collision):
     """The differentiation workload at 16^3 with the regularized collision
-    (Sec. 3) at tau = 0.8: 200 steps, checkpoints every 50."""
+    (Sec. 3; second- and third-order readings) at tau = 0.8: 200 steps,
+    checkpoints every 50."""
     from paper_1601_01237_amd.autograd import LBMFunction
-    say("regularized calibration gradient 16^3 x 200")
+    say(f"{collision} calibration gradient 16^3 x 200")
     n, steps, every = 16, 200, 50
     rho0, target = _calibration_inputs(n)
     G, tau = -1.0, 0.8
     r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
     Gt = torch.tensor(G, dtype=torch.float64, requires_grad=True)
     Tt = torch.tensor(tau, dtype=torch.float64, requires_grad=True)
-    rho = LBMFunction.apply(r0, Gt, Tt, steps, every, None, (0.0, 0.0), "regularized")
+    rho = LBMFunction.apply(r0, Gt, Tt, steps, every, None, (0.0, 0.0), collision)
     tgt = torch.tensor(target, dtype=torch.float32, device="cuda")
     L = 0.5 * ((rho[0].double() - tgt.double()) ** 2).sum()
     L.backward()
 
-    p = olbm.Params(tau=(tau, tau), G=((0.0, G), (G, 0.0)), collision="regularized")
+    p = olbm.Params(tau=(tau, tau), G=((0.0, G), (G, 0.0)), collision=collision)
     L_ref, dG_ref, dtau_ref, drho0_ref = oadj.loss_and_gradient(rho0, p, steps, target)
     e_G = abs(float(Gt.grad) - dG_ref) / abs(dG_ref)
     e_t = abs(float(Tt.grad) - dtau_ref) / abs(dtau_ref)
     e_r = rel_err(r0.grad.cpu().numpy(), drho0_ref)
-    say(f"16^3 regularized calibration: L {float(L.detach()):.6e} vs {L_ref:.6e}; dL/dG {float(Gt.grad):.6e} vs "
+    say(f"16^3 {collision} calibration: L {float(L.detach()):.6e} vs {L_ref:.6e}; dL/dG {float(Gt.grad):.6e} vs "
         f"{dG_ref:.6e} ({e_G:.1e}); dL/dtau {float(Tt.grad):.6e} vs {dtau_ref:.6e} ({e_t:.1e}); dL/drho0 {e_r:.1e}")
     assert abs(float(L.detach()) - L_ref) <= 1e-5 * L_ref
     assert e_G < 1e-3 and e_t < 1e-3 and e_r < 1e-3, (e_G, e_t, e_r)
@@ -319,7 +322,7 @@ def test_adjoint_workspace_size_and_checks(lib):
     """The workspace holds three FP64 partial sums per workgroup of the
     reverse march, whatever the collision, and for 16-bit storage an FP32
     copy of X_t after them; a workspace one byte short, aliased arrays and
-    the third-order regularized reading are refused before anything is
+    16-bit storage with the fields path are refused before anything is
     launched."""
     import ctypes
     from paper_1601_01237_amd.sim import Sim
@@ -359,13 +362,17 @@ def test_adjoint_workspace_size_and_checks(lib):
     assert bool(torch.isfinite(lam_out).all())
     h.close()
     r3 = Sim(rho0, collision="regularized3")
+    r3.set_adjoint_tiling(2, 2)
     work3 = torch.empty(int(lib.lbm_adjoint_work_bytes(r3.ctx)), dtype=torch.uint8, device="cuda")
+    assert work3.numel() == wb["bgk"]
     assert lib.lbm_adjoint_step(r3.ctx, p(r3.state), p(lam_in), p(lam_out), p(work3),
-                                ctypes.c_size_t(work3.numel()), p(dparams), None) == -5  # LBM_ENOTSUP
+                                ctypes.c_size_t(work3.numel()), p(dparams), None) == 0
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(lam_out).all())
     r3.close()
 
 
-@pytest.mark.parametrize("collision,walls", [("bgk", False), ("regularized", True)])
+@pytest.mark.parametrize("collision,walls", [("bgk", False), ("regularized", True), ("regularized3", True)])
 def test_adjoint_tiling_invariance(lib, collision, walls):
     """Every shape and z chunk of the reverse march gives the same lam_t,
     bitwise (only the summation order of dL/dG and dL/dtau changes)."""
@@ -404,7 +411,7 @@ def test_adjoint_tiling_invariance(lib, collision, walls):
         np.testing.assert_allclose(p, params[0], rtol=1e-9, atol=1e-12)
 
 
-@pytest.mark.parametrize("collision", ["bgk", "regularized"])
+@pytest.mark.parametrize("collision", ["bgk", "regularized", "regularized3"])
 @pytest.mark.parametrize("walls", [False, True])
 def test_step_fields_and_reverse_with_fields(lib, walls, collision):
     """lbm_step_fields advances the state exactly as lbm_step and writes the
@@ -462,13 +469,13 @@ def test_step_fields_and_reverse_with_fields(lib, walls, collision):
 
 
 def test_step_fields_refusals(lib):
-    """16-bit storage and the third-order reading have no reverse step, so no
-    fields step; null or aliased buffers are refused."""
+    """16-bit storage has no fields step (its reverse step reads an FP32 copy
+    of X_t); null or aliased buffers are refused."""
     import ctypes
     from paper_1601_01237_amd.sim import Sim
     rho0 = inputs.sphere_droplet((8, 8, 8), radius=2.0, seed=1)
     buf = torch.empty(5 * 512, dtype=torch.float32, device="cuda")
-    for kw in (dict(storage="fp16"), dict(collision="regularized3")):
+    for kw in (dict(storage="fp16"), dict(storage="bf16")):
         s = Sim(rho0, **kw)
         assert s.lib.lbm_step_fields(s.ctx, ctypes.c_void_p(buf.data_ptr())) == -5
         s.close()
@@ -479,7 +486,7 @@ def test_step_fields_refusals(lib):
     s.close()
 
 
-@pytest.mark.parametrize("collision", ["bgk", "regularized"])
+@pytest.mark.parametrize("collision", ["bgk", "regularized", "regularized3"])
 @pytest.mark.parametrize("storage,walls", [("fp16", None), ("bf16", None), ("fp16", "obstacle"), ("bf16", "porous")])
 def test_16bit_reverse_step(lib, storage, walls, collision):
     """The reverse step of a 16-bit context is the FP32 reverse step at the
