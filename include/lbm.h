@@ -103,8 +103,7 @@ typedef enum { LBM_FP32 = 0, LBM_FP16 = 1, LBM_BF16 = 2 } lbm_storage;
  *                    the third order for the energy flux): f^neq adds
  *                    w_i H_i . q / (2 T0^3) with the contracted third-order
  *                    Hermite polynomials H_{i,a} = sum_{b != a} (c_a c_b^2 -
- *                    T0 c_a) and q_a = sum_i H_{i,a} (f_i - f^eq_i).  No
- *                    adjoint (lbm_adjoint_step answers LBM_ENOTSUP).
+ *                    T0 c_a) and q_a = sum_i H_{i,a} (f_i - f^eq_i).
  * F is the exact-difference forcing term in all three. */
 typedef enum { LBM_BGK = 0, LBM_REGULARIZED = 1, LBM_REGULARIZED3 = 2 } lbm_collision;
 
