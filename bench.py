@@ -326,6 +326,7 @@ def main():
         print("[bench] adjoint 96^3", file=sys.stderr, flush=True)
         extra["adjoint_96^3"] = adjoint_cost()
         extra["adjoint_96^3_regularized"] = adjoint_cost(collision="regularized")
+        extra["adjoint_96^3_regularized3"] = adjoint_cost(collision="regularized3")
 
     cpu = None
     if not args.no_cpu:
